@@ -1,0 +1,157 @@
+#!/usr/bin/env python3
+"""Throughput of the Abelian-Higgs leapfrog on one MI355X.
+
+Workload: a 512^3 periodic lattice in the matter era (a ~ tau^2), s = 0,
+lambda0 = 2, e0 = 1, sigma = 1, dx = 0.5, dt = 0.1, seeded random-phase
+initial state, string length and <v^2> measured every 20 steps (the
+configuration the paper times at 512^3, Sec. 3 and Table 2).  A bench step is
+one leapfrog step of the whole lattice (Eqs. (4)-(7)), with the diagnostics
+of Eqs. (9)-(11) on the steps the cadence selects.
+
+Prints ONE JSON line: FP32 storage and arithmetic (FP64 bookkeeping and
+reductions) is the headline ``value``; the FP64 kernel and the plain FP64
+kernel are reported beside it.  ``roofline`` is for the dominant kernel (the
+step kernel) from HIP events around single-step calls; ``cpu_baseline`` times
+the FP64 CPU oracle on a bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E peak, GB/s
+N = 512
+MEASURE_EVERY = 20
+BYTES_PER_SITE = {"f32": 80, "f64": 160}   # read + write of the 10-field state once
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=N, help="lattice extent (default 512)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-secondary", action="store_true", help="FP32 headline only")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "plain", "tiled"])
+    return ap.parse_args()
+
+
+def run_form(AH, torch, n, prec, kernel, steps, warmup):
+    """Time `steps` steps (with the measurement cadence) after `warmup` steps.
+    Returns (site-updates/s, ms/step, mean step-kernel ms)."""
+    # tau_end = n dx / 2, half a light-crossing time (Sec. 2), with a(tau_end) = 1
+    p = AH.Params(n, n, n, precision=prec, dx=0.5, dt=0.1, tau0=0.0, tau_ref=n * 0.5 / 2.0,
+                  era_p=2.0, s=0.0, seed=2024)
+    planes = AH.alloc_planes(p)
+    ctx = AH.Context([p], [planes])
+    if kernel != AH.AH_KERNEL_AUTO:
+        ctx.set_kernel(kernel)
+    stream = torch.cuda.current_stream()
+    ctx.step(warmup)
+    torch.cuda.synchronize()
+
+    # whole-job throughput with the measurement cadence
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    obs = ctx.step(steps, measure_every=MEASURE_EVERY)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    rate = n ** 3 * steps / (ms * 1e-3)
+
+    # dominant kernel: single-step calls bracketed by events on the same stream
+    k = max(5, min(steps, 20))
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(k)]
+    for a, b in evs:
+        a.record(stream)
+        ctx.step(1)
+        b.record(stream)
+    torch.cuda.synchronize()
+    kms = sum(a.elapsed_time(b) for a, b in evs) / k
+    last = obs[-1][0] if obs else None
+    ctx.close()
+    del planes
+    torch.cuda.empty_cache()
+    return rate, ms / steps, kms, last
+
+
+def cpu_baseline():
+    """The FP64 oracle (test infrastructure) on a bounded sample: 256^3, 6 steps."""
+    import oracle as O
+    n, k = 256, 6
+    p = O.Params(n, n, n, tau0=1.0, tau_ref=n * 0.5 / 2, era_p=2.0, s=0.0, seed=2024)
+    st = O.init_random_phase(p)
+    st = O.step(p, 10, st)                     # warm the pages
+    t = time.perf_counter()
+    for i in range(k):
+        st = O.step(p, 11 + i, st)
+    dt = time.perf_counter() - t
+    return {"value": n ** 3 * k / dt, "unit": "site-updates/s", "cores": O.threads(),
+            "kind": "oracle",
+            "sample": f"FP64 CPU oracle, {n}^3 matter era s=0, {k} steps ({dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the multi-GPU "
+              "z-slab decomposition of the lattice is not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1809_00995_amd as AH
+    kern = {"auto": AH.AH_KERNEL_AUTO, "plain": AH.AH_KERNEL_PLAIN,
+            "tiled": AH.AH_KERNEL_TILED}[args.kernel]
+    n, K, W = args.n, args.steps, args.warmup
+
+    rate32, ms32, kms32, last32 = run_form(AH, torch, n, AH.AH_FP32, kern, K, W)
+    print(f"# fp32 {args.kernel}: {rate32:.4g} site-updates/s, {ms32:.3f} ms/step, "
+          f"step kernel {kms32:.3f} ms", file=sys.stderr, flush=True)
+    achieved = BYTES_PER_SITE["f32"] * n ** 3 / (kms32 * 1e-3) / 1e9
+    line = {
+        "metric": "lattice site-updates/s and % HBM roofline, FP32 vs FP64 kernel, 512^3",
+        "value": rate32, "unit": "site-updates/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": ms32, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{n}^3 periodic lattice, matter era a~tau^2, s=0, lambda0=2, "
+                               f"e0=1, sigma=1, dx=0.5, dt=0.1, random-phase init, string "
+                               f"length and <v^2> every {MEASURE_EVERY} steps",
+                   "lattice": [n, n, n], "measure_every": MEASURE_EVERY, "kernel": args.kernel,
+                   "precision": "FP32 fields and stencil, FP64 bookkeeping and reductions"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "step", "bytes_per_site": BYTES_PER_SITE["f32"],
+                     "kernel_ms": kms32},
+    }
+    if last32 is not None:
+        line["last_obs"] = {"step": last32.step, "n_wind": last32.n_wind,
+                            "xi_w": last32.xi_w, "v2_L": last32.v2[0]}
+    if not args.no_secondary:
+        rate64, ms64, kms64, _ = run_form(AH, torch, n, AH.AH_FP64, kern, K, W)
+        print(f"# fp64 {args.kernel}: {rate64:.4g} site-updates/s", file=sys.stderr, flush=True)
+        ach64 = BYTES_PER_SITE["f64"] * n ** 3 / (kms64 * 1e-3) / 1e9
+        line["fp64"] = {"value": rate64, "ms_per_step": ms64, "kernel_ms": kms64,
+                        "achieved_GBs": ach64, "frac": ach64 / HBM_PEAK_GBS}
+        kp = max(10, K // 4)
+        ratep, msp, kmsp, _ = run_form(AH, torch, n, AH.AH_FP64, AH.AH_KERNEL_PLAIN, kp, 2)
+        print(f"# fp64 plain: {ratep:.4g} site-updates/s", file=sys.stderr, flush=True)
+        line["plain_fp64"] = {"value": ratep, "ms_per_step": msp, "kernel_ms": kmsp,
+                              "steps": kp}
+        line["speedup_fp32_vs_plain_fp64"] = rate32 / ratep
+        line["speedup_fp64_vs_plain_fp64"] = rate64 / ratep
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * ah.h -- C ABI of the MI355X (gfx950) Abelian-Higgs lattice library.
+ *
+ * The library advances a local U(1) Abelian-Higgs field -- complex scalar phi
+ * with momentum Pi, link angles A_i with electric fields E_i -- on a periodic
+ * comoving 3D lattice in an FRW background with the staggered leapfrog of
+ * Correia & Martins, arXiv:1809.00995, Sec. 2, Eqs. (4)-(8), and measures the
+ * network diagnostics of Sec. 2, Eqs. (9)-(11): the plaquette winding string
+ * length and the weighted mean square velocity.
+ *
+ * Conventions shared by every entry point
+ *  - Return value: AH_OK (0) or a negative ah_status.  ah_error_string()
+ *    names a code; ah_last_error() gives the message of the last failure on
+ *    a context.  A context is not thread safe: calls on one context must not
+ *    overlap.
+ *  - Device memory: all field storage is owned by the caller (for instance
+ *    one torch tensor per realization) and must outlive the context.  The
+ *    library owns only its small scratch (step counters, coefficients,
+ *    reduction accumulators), allocated in ah_init and released in ah_free.
+ *  - Streams: every GPU operation of a context is issued on the hipStream_t
+ *    given to ah_init (NULL = the default stream).  ah_step is asynchronous
+ *    unless it returns observations; ah_measure and ah_gauss_residual
+ *    synchronise that stream before returning host values.
+ *  - Field layout (struct ah_buffers): 15 planes of nx*ny*nz elements
+ *    (float for AH_FP32, double for AH_FP64), contiguous, site index
+ *    idx = x + nx*(y + ny*z), in the order
+ *      0 phi_re  1 phi_im  2 Pi_re  3 Pi_im  4 A_x  5 A_y  6 A_z
+ *      7 E_x     8 E_y     9 E_z   10 phi_re' 11 phi_im' 12 A_x' 13 A_y' 14 A_z'
+ *    Planes 10-14 are the second copy of phi and A: each step reads phi, A
+ *    from one copy and writes the other.  ah_current_planes() says which
+ *    copy holds the current state.  A state S_n stores phi^n, A^n and the
+ *    half-step momenta Pi^{n-1/2}, E^{n-1/2}.  A_i is the raw link angle
+ *    (never reduced modulo 2 pi).
+ */
+#ifndef AH_H
+#define AH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ah_status {
+    AH_OK = 0,
+    AH_E_INVALID = -1,    /* bad argument, NULL pointer, bad extents, misaligned buffer */
+    AH_E_NOMEM = -2,      /* host or device allocation of library scratch failed       */
+    AH_E_HIP = -3,        /* a HIP runtime call failed (message names it)               */
+    AH_E_DOMAIN = -4,     /* parameters outside the method's domain (CFL, s, era, a)    */
+    AH_E_STATE = -5,      /* call not valid in the context's current state              */
+    AH_E_NONFINITE = -6   /* a measurement found non-finite field values                */
+} ah_status;
+
+enum { AH_FP64 = 0, AH_FP32 = 1 };
+
+enum {
+    AH_INIT_RANDOM_PHASE = 0, /* |phi| = sigma, uniform random phase, all else 0 (Sec. 2) */
+    AH_INIT_VACUUM = 1,       /* phi = sigma, all else 0                                   */
+    AH_INIT_NONE = 2          /* keep the caller's planes 0-9 as S_{step0} (resume)        */
+};
+
+enum {
+    AH_KERNEL_AUTO = 0,       /* the library's fastest variant for the shape and precision */
+    AH_KERNEL_PLAIN = 1,      /* one thread per site, every neighbour read from memory     */
+    AH_KERNEL_TILED = 2       /* z-streaming tiles with LDS-staged phasors and plaquettes  */
+};
+
+/* Problem statement of one realization (Sec. 2 and Sec. 4 of the paper). */
+typedef struct ah_params {
+    int32_t nx, ny, nz;   /* periodic extents, each >= 4, nx*ny*nz < 2^31; the tiled
+                             kernel needs nx a multiple of 64                          */
+    int32_t precision;    /* AH_FP64 or AH_FP32: field storage and stencil arithmetic;
+                             time bookkeeping and reductions are FP64 in both            */
+    double dx, dt;        /* lattice spacing, conformal time step; dt/dx < 1/sqrt(3)     */
+    double tau0, tau_ref; /* tau_n = tau0 + n dt; a(tau) = (max(tau,0)/tau_ref)^era_p    */
+    double era_p;         /* 0 flat (a = 1), 1 radiation (a ~ tau), 2 matter (a ~ tau^2) */
+    double s;             /* 0 <= s <= 1: couplings e0 a^(s-1), lambda0 a^(2(s-1)), Eq. (8) */
+    double lambda0, e0, sigma; /* scalar coupling, gauge coupling, vacuum expectation   */
+    uint64_t seed;        /* random-phase seed (AH_INIT_RANDOM_PHASE)                   */
+    int32_t init;         /* AH_INIT_*                                                  */
+    int32_t reserved;     /* must be 0                                                  */
+    int64_t step0;        /* step index n of the initial state (resume from step0)      */
+    int64_t n_end;        /* 0: no limit; else the realization stops at S_{n_end} (its
+                             tau_end): further steps leave it unchanged                 */
+} ah_params;
+
+/* Caller-owned device memory of one realization: 15 planes, see above.
+ * Alignment: 256 bytes. */
+typedef struct ah_buffers {
+    void *planes;
+} ah_buffers;
+
+/* Diagnostics of one state S_n (Sec. 2, Eqs. (9)-(11)).  Densities are the
+ * conformal densities of S_n as stored, with a = a(tau_n):
+ *   L = a^2 K - a^2 G + g (EE - BB) - h V,  rho = a^2 K + a^2 G + g (EE + BB) + h V,
+ *   K = |Pi|^2, G = dx^-2 sum_i |e^{iA_i} phi^{x+i} - phi^x|^2, EE = dx^-2 sum_i E_i^2,
+ *   BB = 2 dx^-4 sum_{xy,yz,zx} (1 - cos Xi), V = (|phi|^2 - sigma^2)^2 / 4,
+ *   g = a^(2(1-s)) / (2 e0^2), h = lambda0 a^(2+2s). */
+typedef struct ah_obs {
+    int64_t step;
+    double tau, a;
+    int64_t n_wind;          /* sum over plaquettes of |W|, Eq. (11)                  */
+    int64_t n_wind_dir[3];   /* per orientation xy, yz, zx                             */
+    int64_t net_wind_dir[3]; /* signed sums per orientation (zero on a periodic box)  */
+    int64_t n_pierced;       /* plaquettes with W != 0                                */
+    double length, xi_w;     /* (pi/6) dx n_wind ; sqrt(V_box / length)               */
+    double sum_lag, xi_l;    /* dx^3 sum L ; a sqrt(-2 pi sigma^2 V_box / sum_lag), Eq. (9) */
+    double num[3], den[3];   /* dx^3 sum K X, dx^3 sum G X for X = L, V, rho          */
+    double v2[3];            /* <v^2>_X = 2R/(1+R), R = num/den, Eqs. (9)-(10)        */
+    double kin, grad, elec, mag, pot, energy; /* dx^3 sums of the parts of rho      */
+    int64_t nonfinite;       /* sites holding a non-finite field value               */
+} ah_obs;
+
+typedef struct ah_ctx ah_ctx;
+
+/* Text for a status code (static storage). */
+const char *ah_error_string(int code);
+
+/* Message of the last failed call on ctx (valid until the next call). */
+const char *ah_last_error(const ah_ctx *ctx);
+
+/*
+ * Create a context for n_real >= 1 independent realizations.  p[r] and buf[r]
+ * describe realization r; all realizations share one precision.  Validates
+ * the parameters (extents, alignment, CFL dt/dx < 1/sqrt(3), 0 <= s <= 1,
+ * era_p >= 0, tau_ref > 0, a(tau_{step0 + 1/2}) > 0), allocates the scratch,
+ * then writes the initial state on the stream: the random-phase initial
+ * condition of Sec. 2 (theta = 2 pi u - pi, u from SplitMix64 output number
+ * idx+1 of generator p[r].seed), the vacuum, or nothing (AH_INIT_NONE: the
+ * caller's planes 0-9 hold S_{step0}).  On failure *ctx is NULL and nothing
+ * is allocated.  hip_stream is a hipStream_t or NULL.
+ */
+int ah_init(ah_ctx **ctx, int32_t n_real, const ah_params *p, const ah_buffers *buf,
+            void *hip_stream);
+
+/*
+ * Advance every realization by nsteps (>= 0) leapfrog steps, Eqs. (4)-(7):
+ * S_n -> S_{n+1} (a realization that has reached its n_end stays there).
+ * With measure_every = k > 0, every state S_n with n % k == 0 met before its
+ * update is measured (as ah_measure would), and the observations are written
+ * to out[j * n_real + r] for the j-th step of the call that measured; slots
+ * of realizations that did not measure at that step have step = -1.
+ * *n_out receives the number of slots written per realization.
+ * out_cap is the capacity of out in states per realization; the call fails
+ * with AH_E_INVALID, before any work, if it is too small.  With out == NULL
+ * (and measure_every = 0) the call only enqueues work and returns at once.
+ * Returns AH_E_NONFINITE if a measurement saw non-finite values.
+ */
+int ah_step(ah_ctx *ctx, int64_t nsteps, int32_t measure_every, ah_obs *out,
+            int64_t out_cap, int64_t *n_out);
+
+/*
+ * Measure the current state S_n of every realization into out[r] (host
+ * array of n_real).  wind_dev, if not NULL, is a device array that receives,
+ * per realization, 3 int8 planes (xy, yz, zx plaquette at site x) of W,
+ * realizations back to back.  Synchronises the stream.
+ */
+int ah_measure(ah_ctx *ctx, ah_obs *out, int8_t *wind_dev);
+
+/*
+ * Gauss-law residual of the current state (discrete Noether charge of the
+ * lattice action under time-independent gauge transformations, conserved by
+ * Eqs. (4)-(7); checked in Sec. 4):
+ *   G_x = sum_i (E_i^x - E_i^{x-i}) a_-^(2(1-s)) / e0^2 + 2 dx^2 a_-^2 Im(conj(phi^x) Pi^x),
+ * a_- = a(tau_{n-1/2}).  max_abs[r], rms[r]: host arrays of n_real.
+ * Synchronises the stream.
+ */
+int ah_gauss_residual(ah_ctx *ctx, double *max_abs, double *rms);
+
+/* Plane index (0-14) of each of the 10 fields phi_re, phi_im, Pi_re, Pi_im,
+ * A_x, A_y, A_z, E_x, E_y, E_z of realization r in the current state. */
+int ah_current_planes(const ah_ctx *ctx, int32_t r, int32_t plane_of_field[10]);
+
+/* Step index n of the current state of realization r. */
+int ah_current_step(const ah_ctx *ctx, int32_t r, int64_t *n);
+
+/*
+ * Select the step-kernel variant (AH_KERNEL_*) and, for AH_KERNEL_TILED, the
+ * tile: tile_y rows of 64 sites per block (1..16) and chunk_z planes per
+ * block along z (1..nz).  0 picks the library default.  AH_KERNEL_TILED
+ * needs nx % 64 == 0 in every realization (AH_E_INVALID otherwise).  Results do not
+ * depend on the choice beyond floating-point rounding of the same formulas;
+ * the tiled variants of one precision agree bit for bit.
+ */
+int ah_set_kernel(ah_ctx *ctx, int32_t kernel, int32_t tile_y, int32_t chunk_z);
+
+/* Release the context's scratch (not the caller's planes).  NULL is a no-op. */
+int ah_free(ah_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AH_H */

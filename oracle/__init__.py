@@ -93,6 +93,7 @@ def _load():
         lib.or_step.argtypes = [P(_Params), C.c_int64, D, D]
         lib.or_measure.argtypes = [P(_Params), C.c_int64, D, P(_Obs), C.c_void_p]
         lib.or_gauss.argtypes = [P(_Params), C.c_int64, D, D, D, C.c_void_p]
+        lib.or_threads.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -107,6 +108,11 @@ def _state(p: Params, st) -> np.ndarray:
     if st.shape != p.shape:
         raise ValueError(f"state shape {st.shape} != {p.shape}")
     return st
+
+
+def threads() -> int:
+    """Threads the oracle's parallel loops use."""
+    return int(_load().or_threads())
 
 
 def scale_factor(p: Params, tau: float) -> float:

@@ -33,6 +33,9 @@
 #include "ah_oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -446,4 +449,13 @@ void or_gauss(const or_params *p, int64_t n, const double *st, double *max_abs,
     *rms = sqrt(sq / (double)N);
     free(pmax);
     free(psq);
+}
+
+int or_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -74,6 +74,9 @@ void or_measure(const or_params *p, int64_t n, const double *state,
 void or_gauss(const or_params *p, int64_t n, const double *state,
               double *max_abs, double *rms, double *gmap);
 
+/* Number of threads the parallel loops use (OpenMP), 1 without OpenMP. */
+int or_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,100 @@
+// ah_device.hpp -- device-side types and helpers of the gfx950 Abelian-Higgs library.
+//
+// Every kernel reads its realization's description (RealDesc) and the FP64
+// step bookkeeping (Coef) from device memory, so kernel arguments are the same
+// on every step and a sequence of steps can be replayed from a captured graph.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ah.h"
+
+namespace ah {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double kTwoPi = 6.28318530717958647692528676655900577;
+
+// Plane numbers of the caller's 15-plane buffer.
+enum : int { P_PHR = 0, P_PHI = 1, P_PIR = 2, P_PII = 3, P_AX = 4, P_EX = 7,
+             P_PHR2 = 10, P_AX2 = 12 };
+
+// Static description of one realization (written once by ah_init).
+struct RealDesc {
+    char *base;            // 15 planes of N elements
+    int32_t nx, ny, nz;
+    int32_t elem;          // bytes per element (4 or 8)
+    int64_t N;             // nx * ny * nz
+    double dx, dt, tau0, tau_ref, era_p, s, lambda0, e0, sigma;
+    int64_t step0, n_end;
+};
+
+// FP64 bookkeeping for advancing realization r from S_n (written on the
+// device by k_bookkeep before each step or measurement).
+struct Coef {
+    int64_t n;             // step index of the state being read
+    int32_t active;        // 0 once the realization has reached n_end
+    int32_t parity;        // 0: phi, A in planes 0,1,4-6; 1: in planes 10-14
+    double tau, a_m, a_0, a_p;
+    double c1, c2, c3;     // Pi update, Eq. (4)
+    double d1, d2, d3;     // E update, Eq. (5)
+};
+
+// Raw per-measurement accumulators (sums over sites, before the dx^3 factor).
+enum : int { A_KIN, A_GRAD, A_ELEC, A_MAG, A_POT, A_LAG,
+             A_NUM_L, A_NUM_V, A_NUM_R, A_DEN_L, A_DEN_V, A_DEN_R, A_COUNT };
+enum : int { C_W0, C_W1, C_W2, C_N0, C_N1, C_N2, C_PIERCED, C_NONFIN, C_COUNT };
+
+struct Acc {
+    double s[A_COUNT];
+    unsigned long long c[C_COUNT];   // two's complement for signed sums
+};
+
+// One measurement slot: the sums, the bookkeeping of the measured state, and
+// whether a measurement kernel wrote it.  Cleared to zero before use.
+struct Slot {
+    Acc acc;
+    Coef c;
+    int32_t measured;
+    int32_t pad;
+};
+
+template <typename T> __device__ __forceinline__ T* plane(const RealDesc &d, int k) {
+    return reinterpret_cast<T*>(d.base + (size_t)k * (size_t)d.N * sizeof(T));
+}
+
+// Current-state plane of field f (0..9) for the given ping-pong parity.
+__host__ __device__ __forceinline__ int field_plane(int f, int parity) {
+    if (!parity)
+        return f;
+    if (f < 2)
+        return P_PHR2 + f;
+    if (f >= 4 && f < 7)
+        return P_AX2 + (f - 4);
+    return f;
+}
+
+__device__ __forceinline__ void sincos_t(float x, float *s, float *c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sincos_t(double x, double *s, double *c) { sincos(x, s, c); }
+__device__ __forceinline__ float sin_t(float x) { return sinf(x); }
+__device__ __forceinline__ double sin_t(double x) { return sin(x); }
+
+// ---------------------------------------------------------------- reductions
+// Sum over a 64-lane wavefront; lane 0 ends with the total.
+template <typename V> __device__ __forceinline__ V wave_sum(V v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename V> __device__ __forceinline__ V wave_max(V v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        V o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+} // namespace ah

@@ -1,0 +1,94 @@
+// k_common.hpp -- small kernels shared by all step variants: FP64 time
+// bookkeeping, the seeded initial condition, scratch clearing.
+#pragma once
+
+#include "ah_device.hpp"
+
+namespace ah {
+
+__device__ __forceinline__ double scale_factor(const RealDesc &d, double tau) {
+    // a(tau) = (max(tau,0)/tau_ref)^p; p = 1 radiation, 2 matter (Sec. 4), 0 flat.
+    double t = tau > 0.0 ? tau : 0.0;
+    return pow(t / d.tau_ref, d.era_p);
+}
+
+// FP64 bookkeeping of Eqs. (4), (5) and (8), one thread per realization.
+// Substituting e = e0 a^(s-1) and lambda = lambda0 a^(2(s-1)) into the
+// coefficients of Eqs. (4)-(5) and cancelling powers of a gives forms that
+// stay finite at a(tau0) = 0:
+//   c1 = (a_-/a_+)^2, c2 = dt/dx^2 (a_0/a_+)^2, c3 = dt lambda0/2 (a_0/a_+)^2 a_0^(2s),
+//   d1 = (a_-/a_+)^(2(1-s)), d2 = dt/dx^2 (a_0/a_+)^(2(1-s)), d3 = 2 dt e0^2 (a_0/a_+)^2 a_+^(2s).
+// With advance != 0 the realization's step counter moves on to n+1 (the
+// coefficients describe the update of S_n); frozen realizations stay.
+__global__ void k_bookkeep(const RealDesc *desc, int64_t *step, Coef *coef, int nreal,
+                           int advance) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nreal)
+        return;
+    const RealDesc d = desc[r];
+    const int64_t n = step[r];
+    Coef c;
+    c.n = n;
+    c.active = (d.n_end <= 0 || n < d.n_end) ? 1 : 0;
+    c.parity = (int)((n - d.step0) & 1);
+    c.tau = d.tau0 + (double)n * d.dt;
+    c.a_m = scale_factor(d, c.tau - 0.5 * d.dt);
+    c.a_0 = scale_factor(d, c.tau);
+    c.a_p = scale_factor(d, c.tau + 0.5 * d.dt);
+    const double q = c.a_m / c.a_p, rr = c.a_0 / c.a_p;
+    const double h = d.dt / (d.dx * d.dx);
+    c.c1 = q * q;
+    c.c2 = h * rr * rr;
+    c.c3 = d.dt * 0.5 * d.lambda0 * rr * rr * pow(c.a_0, 2.0 * d.s);
+    c.d1 = pow(q, 2.0 * (1.0 - d.s));
+    c.d2 = h * pow(rr, 2.0 * (1.0 - d.s));
+    c.d3 = 2.0 * d.dt * d.e0 * d.e0 * rr * rr * pow(c.a_p, 2.0 * d.s);
+    coef[r] = c;
+    if (advance && c.active)
+        step[r] = n + 1;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): output number k of the generator
+// seeded with `seed` is the fixed 64-bit mix of seed + k * 0x9e3779b97f4a7c15.
+__device__ __forceinline__ uint64_t splitmix64_output(uint64_t seed, uint64_t k) {
+    uint64_t v = seed + k * 0x9e3779b97f4a7c15ull;
+    v = (v ^ (v >> 30)) * 0xbf58476d1ce4e5b9ull;
+    v = (v ^ (v >> 27)) * 0x94d049bb133111ebull;
+    return v ^ (v >> 31);
+}
+
+// Initial state (Sec. 2, after Eq. (8)): phi = sigma e^{i theta} with
+// theta = 2 pi u - pi, u = (output idx+1 >> 11) 2^-53, computed in FP64 and
+// rounded once to the storage type; Pi = A = E = 0 (Gauss's law holds).  The
+// second phi/A copy is cleared too.  kind: AH_INIT_RANDOM_PHASE or VACUUM.
+template <typename T>
+__global__ void __launch_bounds__(256) k_init(const RealDesc *desc, int r, int kind, uint64_t seed) {
+    const RealDesc d = desc[r];
+    const T zero = 0;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < d.N;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        double pr = d.sigma, pi = 0.0;
+        if (kind == AH_INIT_RANDOM_PHASE) {
+            uint64_t bits = splitmix64_output(seed, (uint64_t)idx + 1u) >> 11;
+            double theta = kTwoPi * ((double)bits * 0x1.0p-53) - kPi;
+            double s, c;
+            sincos(theta, &s, &c);
+            pr = d.sigma * c;
+            pi = d.sigma * s;
+        }
+        plane<T>(d, P_PHR)[idx] = (T)pr;
+        plane<T>(d, P_PHI)[idx] = (T)pi;
+        for (int k = 2; k < 15; ++k)
+            plane<T>(d, k)[idx] = zero;
+    }
+}
+
+// Clear n 64-bit words (used instead of a memset so the step sequence can be
+// graph-captured).
+__global__ void k_zero_u64(unsigned long long *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+} // namespace ah

@@ -1,0 +1,93 @@
+"""The C-ABI library on the CPU: it loads, exports every entry point that
+include/ah.h declares, and rejects invalid problems before touching a GPU."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1809_00995_amd as AH
+from paper_1809_00995_amd import ah as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "ah.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ah_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_entry_point():
+    lib = AH.load_library()
+    names = declared_functions()
+    assert len(names) == 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(B.EXPORTED) == names
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """ctypes mirrors of ah_params, ah_buffers and ah_obs: every field offset
+    and the total size equal what a C compiler makes of include/ah.h."""
+    structs = {"ah_params": B._Params, "ah_buffers": B._Buffers, "ah_obs": B._Obs}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ah.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        cname, f, v = line.split()
+        py = structs[cname]
+        got = C.sizeof(py) if f == "size" else getattr(py, f).offset
+        assert got == int(v), (cname, f)
+
+
+def _init(**kw):
+    lib = AH.load_library()
+    p = AH.Params(64, 8, 8, **kw)._c()
+    b = B._Buffers(4096)                      # never dereferenced: validation fails first
+    ctx = C.c_void_p()
+    rc = lib.ah_init(C.byref(ctx), 1, C.byref(p), C.byref(b), None)
+    return rc, lib.ah_last_error(None).decode(), ctx
+
+
+@pytest.mark.parametrize("kw,code,text", [
+    (dict(dt=0.3), B.AH_E_DOMAIN, "CFL"),
+    (dict(s=1.5), B.AH_E_DOMAIN, "s must"),
+    (dict(era_p=-1.0), B.AH_E_DOMAIN, "era_p"),
+    (dict(tau_ref=0.0), B.AH_E_DOMAIN, "tau_ref"),
+    (dict(tau0=-5.0), B.AH_E_DOMAIN, "a(tau"),
+    (dict(init=7), B.AH_E_INVALID, "init"),
+    (dict(n_end=-2), B.AH_E_INVALID, "n_end"),
+])
+def test_invalid_parameters_are_rejected(kw, code, text):
+    rc, msg, ctx = _init(**kw)
+    assert rc == code and text in msg and not ctx.value
+
+
+def test_bad_extents_alignment_and_null():
+    lib = AH.load_library()
+    ctx = C.c_void_p()
+    p = AH.Params(2, 8, 8)._c()
+    b = B._Buffers(4096)
+    assert lib.ah_init(C.byref(ctx), 1, C.byref(p), C.byref(b), None) == B.AH_E_INVALID
+    p = AH.Params(64, 8, 8)._c()
+    b = B._Buffers(4096 + 16)
+    assert lib.ah_init(C.byref(ctx), 1, C.byref(p), C.byref(b), None) == B.AH_E_INVALID
+    assert "aligned" in lib.ah_last_error(None).decode()
+    assert lib.ah_init(C.byref(ctx), 0, C.byref(p), C.byref(b), None) == B.AH_E_INVALID
+    assert lib.ah_init(None, 1, C.byref(p), C.byref(b), None) == B.AH_E_INVALID
+    mixed = (B._Params * 2)(AH.Params(64, 8, 8)._c(), AH.Params(64, 8, 8, precision=1)._c())
+    bufs = (B._Buffers * 2)(B._Buffers(4096), B._Buffers(8192))
+    assert lib.ah_init(C.byref(ctx), 2, mixed, bufs, None) == B.AH_E_INVALID
+    assert lib.ah_step(None, 1, 0, None, 0, None) == B.AH_E_INVALID
+    assert lib.ah_free(None) == B.AH_OK
+    assert lib.ah_error_string(B.AH_E_NONFINITE) == b"non-finite field values"

@@ -1,0 +1,246 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+the same seeded inputs.
+
+Tolerances: FP64 kernels 1e-12 (max-norm relative per field group) after tens
+of steps -- the two sides evaluate the same formulas in a different order and
+with different libm implementations, so they differ by rounding only.  FP32
+kernels: 1e-5 on fields after 10 steps, 1e-3 on string length and <v^2> at
+the end, windings compared plaquette by plaquette with mismatches allowed only
+on plaquettes with a link whose phase argument lies within 1e-6 of pi.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from tests import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+AH = pytest.importorskip("paper_1809_00995_amd")
+from tests.gpu_util import (ambiguous_links, fields_np, group_errors, oracle_params,  # noqa: E402
+                            plaquette_touches, upload)
+
+KERNELS = [AH.AH_KERNEL_PLAIN, AH.AH_KERNEL_TILED]
+SHAPES = [(64, 12, 10), (128, 6, 5)]
+
+
+def _ctx(p, planes, kernel=AH.AH_KERNEL_AUTO, tile_y=0, chunk_z=0):
+    c = AH.Context([p], [planes])
+    if kernel != AH.AH_KERNEL_AUTO:
+        c.set_kernel(kernel, tile_y, chunk_z)
+    return c
+
+
+def _print_case(**kw):
+    print("CASE", " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+@pytest.mark.parametrize("prec", [AH.AH_FP64, AH.AH_FP32])
+def test_init_random_phase_matches_oracle(O, prec):
+    _print_case(test="init", prec=prec)
+    p = AH.Params(32, 32, 32, precision=prec, seed=12345)
+    t = AH.alloc_planes(p)
+    with AH.Context([p], [t]) as c:
+        got = fields_np(c)
+    ref = O.init_random_phase(oracle_params(O, p))
+    if prec == AH.AH_FP64:
+        assert np.abs(got - ref).max() < 1e-15
+    else:
+        ref32 = ref.astype(np.float32).astype(np.float64)
+        ulp = np.spacing(np.abs(ref32).astype(np.float32)).astype(np.float64)
+        assert (np.abs(got - ref32) <= ulp).all()
+        assert (got == ref32).mean() > 0.999
+
+
+@pytest.mark.parametrize("kernel", KERNELS, ids=["plain", "tiled"])
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("era,s", [(0.0, 0.0), (1.0, 1.0), (2.0, 0.0), (1.0, 0.5)])
+def test_step_fp64_random_state(O, kernel, shape, era, s):
+    _print_case(test="step_fp64", kernel=kernel, shape=shape, era=era, s=s)
+    nx, ny, nz = shape
+    p = AH.Params(nx, ny, nz, precision=AH.AH_FP64, tau0=1.0, tau_ref=2.0, era_p=era, s=s,
+                  init=AH.AH_INIT_NONE)
+    st = I.random_state(shape, seed=101)
+    op = oracle_params(O, p)
+    with _ctx(p, upload(p, st), kernel) as c:
+        ref = st
+        for n_done, k in ((1, 1), (10, 9)):
+            c.step(k)
+            ref, _ = O.run(op, ref, n_done - k, k)
+            err = group_errors(fields_np(c), ref)
+            assert max(err.values()) < 1e-12, (n_done, err)
+
+
+@pytest.mark.parametrize("kernel", KERNELS, ids=["plain", "tiled"])
+def test_step_fp32_random_state(O, kernel):
+    """FP32 storage and arithmetic vs the FP64 oracle from the FP32-rounded input:
+    1e-5 relative per field group after 10 steps."""
+    shape = (64, 12, 10)
+    _print_case(test="step_fp32", kernel=kernel, shape=shape)
+    p = AH.Params(*shape, precision=AH.AH_FP32, tau0=2.0, tau_ref=4.0, era_p=1.0, s=1.0,
+                  init=AH.AH_INIT_NONE)
+    st = I.random_state(shape, seed=202).astype(np.float32).astype(np.float64)
+    with _ctx(p, upload(p, st), kernel) as c:
+        c.step(10)
+        got = fields_np(c)
+    ref, _ = O.run(oracle_params(O, p), st, 0, 10)
+    err = group_errors(got, ref)
+    assert max(err.values()) < 1e-5, err
+
+
+def _compare_obs(g, o, rel):
+    assert g.step == o.step
+    assert g.n_wind_dir == o.n_wind_dir and g.net_wind_dir == o.net_wind_dir
+    assert g.n_pierced == o.n_pierced and g.nonfinite == o.nonfinite == 0
+    for k in ("length", "sum_lag", "kin", "grad", "elec", "mag", "pot", "energy", "xi_w"):
+        assert getattr(g, k) == pytest.approx(getattr(o, k), rel=rel, abs=1e-300), k
+    for k in ("num", "den"):
+        # atol: sums of roundoff-sized terms (e.g. sum G V at |phi| = sigma) carry no digits
+        assert np.allclose(getattr(g, k), getattr(o, k), rtol=rel, atol=1e-20), k
+    for gv, ov in zip(g.v2, o.v2):
+        assert (math.isnan(gv) and math.isnan(ov)) or gv == pytest.approx(ov, rel=rel, abs=1e-14)
+    if math.isnan(o.xi_l):
+        assert math.isnan(g.xi_l)
+    else:
+        assert g.xi_l == pytest.approx(o.xi_l, rel=rel)
+
+
+def test_config_32cubed_fp64_run(O):
+    """32^3, FP64, radiation, s = 1, random phase, 80 steps to tau = 8 with
+    string length and <v^2> every 10 steps: every observable vs the oracle."""
+    _print_case(test="c1_run")
+    p = AH.Params(32, 32, 32, precision=AH.AH_FP64, tau0=0.0, tau_ref=8.0, era_p=1.0, s=1.0,
+                  seed=1)
+    op = oracle_params(O, p)
+    with AH.Context([p], [AH.alloc_planes(p)]) as c:
+        obs = c.step(80, measure_every=10)
+        mx, _ = c.gauss_residual()
+        got = fields_np(c)
+    st, oobs = O.run(op, O.init_random_phase(op), 0, 80, measure_every=10)
+    assert len(obs) == len(oobs) == 8
+    for (g,), o in zip(obs, oobs):
+        _compare_obs(g, o, 1e-9)
+    assert mx[0] < 1e-12
+    assert max(group_errors(got, st).values()) < 1e-10
+
+
+@pytest.mark.parametrize("prec", [AH.AH_FP64, AH.AH_FP32])
+def test_measure_and_wind_map_match_oracle(O, prec):
+    """Standalone measurement of a generic state, and the winding map plaquette
+    by plaquette on identical input fields."""
+    shape = (64, 10, 9)
+    _print_case(test="measure", prec=prec)
+    p = AH.Params(*shape, precision=prec, tau0=3.0, tau_ref=4.0, era_p=2.0, s=0.0,
+                  init=AH.AH_INIT_NONE, step0=7)
+    st = I.random_state(shape, seed=303, amp_a=2.5)
+    if prec == AH.AH_FP32:
+        st = st.astype(np.float32).astype(np.float64)
+    with AH.Context([p], [upload(p, st)]) as c:
+        (g,), (w,) = c.measure(wind=True)
+        w = w.cpu().numpy().astype(np.int64)
+    o = O.measure(oracle_params(O, p), 7, st, wind_map=True)
+    diff = w != o.wind
+    allowed = plaquette_touches(ambiguous_links(st))
+    assert not (diff & ~allowed).any()
+    print("winding mismatches (all at ambiguous links):", int(diff.sum()))
+    if not diff.any():
+        _compare_obs(g, o, 1e-10)
+    else:
+        assert g.energy == pytest.approx(o.energy, rel=1e-10)
+
+
+@pytest.mark.parametrize("prec", [AH.AH_FP64, AH.AH_FP32])
+def test_gauss_residual_matches_oracle(O, prec):
+    shape = (64, 7, 6)
+    _print_case(test="gauss", prec=prec)
+    p = AH.Params(*shape, precision=prec, tau0=2.0, tau_ref=3.0, era_p=1.0, s=0.5,
+                  init=AH.AH_INIT_NONE, step0=4)
+    st = I.random_state(shape, seed=404)
+    if prec == AH.AH_FP32:
+        st = st.astype(np.float32).astype(np.float64)
+    with AH.Context([p], [upload(p, st)]) as c:
+        mx, rms = c.gauss_residual()
+    omx, orms = O.gauss(oracle_params(O, p), 4, st)
+    assert mx[0] == pytest.approx(omx, rel=1e-12)
+    assert rms[0] == pytest.approx(orms, rel=1e-12)
+
+
+def test_nonfinite_is_reported():
+    _print_case(test="nonfinite")
+    p = AH.Params(64, 8, 8, precision=AH.AH_FP32, init=AH.AH_INIT_VACUUM, tau0=1.0)
+    t = AH.alloc_planes(p)
+    with AH.Context([p], [t]) as c:
+        t[8, 3, 4, 5] = float("nan")
+        with pytest.raises(AH.AHError) as e:
+            c.measure()
+        assert e.value.code == AH.ah.AH_E_NONFINITE
+
+
+@pytest.mark.parametrize("prec", [AH.AH_FP64, AH.AH_FP32])
+def test_vacuum_stays_bitwise(prec):
+    _print_case(test="vacuum", prec=prec)
+    p = AH.Params(64, 8, 8, precision=prec, init=AH.AH_INIT_VACUUM, tau0=0.0, tau_ref=2.0)
+    with AH.Context([p], [AH.alloc_planes(p)]) as c:
+        c.step(25)
+        got = c.fields()
+    ref = torch.zeros_like(got)
+    ref[0] = 1.0
+    assert torch.equal(got, ref)
+
+
+@pytest.mark.parametrize("prec", [AH.AH_FP64, AH.AH_FP32])
+def test_checkpoint_resume_is_bitwise(prec):
+    """Copy the state out at step 12, resume it in a fresh context with
+    AH_INIT_NONE and step0 = 12: identical to the uninterrupted run."""
+    _print_case(test="resume", prec=prec)
+    p = AH.Params(64, 16, 8, precision=prec, tau0=0.0, tau_ref=4.0, era_p=2.0, s=0.0, seed=9)
+    with AH.Context([p], [AH.alloc_planes(p)]) as c:
+        c.step(12)
+        mid = c.fields().clone()
+        c.step(9)
+        full = c.fields().clone()
+    q = AH.Params(**{**p.__dict__, "init": AH.AH_INIT_NONE, "step0": 12})
+    t = AH.alloc_planes(q)
+    t[:10] = mid
+    with AH.Context([q], [t]) as c:
+        c.step(9)
+        assert c.current_step() == 21
+        assert torch.equal(c.fields(), full)
+
+
+def test_batch_equals_solo_and_n_end():
+    """Realizations of different sizes and eras in one context advance exactly
+    as they do alone; a realization stops at its n_end."""
+    _print_case(test="batch")
+    ps = [AH.Params(64, 8, 8, precision=AH.AH_FP32, tau_ref=2.0, era_p=1.0, s=1.0, seed=1),
+          AH.Params(64, 16, 4, precision=AH.AH_FP32, tau_ref=3.0, era_p=2.0, s=0.0, seed=2,
+                    n_end=7),
+          AH.Params(128, 4, 6, precision=AH.AH_FP32, tau_ref=1.0, era_p=1.0, s=0.0, seed=3)]
+    with AH.Context(ps, [AH.alloc_planes(p) for p in ps]) as c:
+        c.step(11)
+        batch = [c.fields(r).clone() for r in range(3)]
+        steps = [c.current_step(r) for r in range(3)]
+    assert steps == [11, 7, 11]
+    for r, p in enumerate(ps):
+        with AH.Context([p], [AH.alloc_planes(p)]) as c:
+            c.step(11)
+            assert torch.equal(c.fields(), batch[r]), r
+
+
+def test_fused_schedule_matches_separate_measure(O):
+    """ah_step's measurements equal ah_measure on the same states."""
+    _print_case(test="fused_schedule")
+    p = AH.Params(64, 8, 8, precision=AH.AH_FP64, tau_ref=2.0, seed=4)
+    with AH.Context([p], [AH.alloc_planes(p)]) as c:
+        c.step(5)
+        obs = c.step(10, measure_every=5)
+    with AH.Context([p], [AH.alloc_planes(p)]) as c:
+        c.step(5)
+        (m5,) = c.measure()
+        c.step(5)
+        (m10,) = c.measure()
+    assert [o[0].step for o in obs] == [5, 10]
+    for (g,), m in zip(obs, (m5, m10)):
+        assert g.n_wind == m.n_wind and g.energy == pytest.approx(m.energy, rel=1e-13)
