@@ -176,8 +176,8 @@ int ah_current_step(const ah_ctx *ctx, int32_t r, int64_t *n);
 
 /*
  * Select the step-kernel variant (AH_KERNEL_*) and, for AH_KERNEL_TILED, the
- * tile: tile_y rows of 64 sites per block (1..16) and chunk_z planes per
- * block along z (1..nz).  0 picks the library default.  AH_KERNEL_TILED
+ * tile: tile_y rows of 64 sites per block (2, 4, 8, or 16 for FP32) and
+ * chunk_z planes per block along z (>= 1).  0 picks the library default.  AH_KERNEL_TILED
  * needs nx % 64 == 0 in every realization (AH_E_INVALID otherwise).  Results do not
  * depend on the choice beyond floating-point rounding of the same formulas;
  * the tiled variants of one precision agree bit for bit.

@@ -152,7 +152,8 @@ bool tiled_ok(const ah_ctx *c) {
 int launch_step(ah_ctx *c, int r) {
     const ah_params &q = c->p[r];
     const int64_t N = (int64_t)q.nx * q.ny * q.nz;
-    const bool tiled = c->kernel == AH_KERNEL_TILED;
+    const bool tiled = c->kernel == AH_KERNEL_TILED ||
+                       (c->kernel == AH_KERNEL_AUTO && q.nx % 64 == 0);
     if (tiled) {
         int rc = launch_step_tiled(c->prec == AH_FP64, c->d_desc, c->d_coef, r, q.nx, q.ny, q.nz,
                                    c->tile_y, c->chunk_z, c->stream);
@@ -477,8 +478,8 @@ int ah_set_kernel(ah_ctx *c, int32_t kernel, int32_t tile_y, int32_t chunk_z) {
     c->err.clear();
     if (kernel < AH_KERNEL_AUTO || kernel > AH_KERNEL_TILED)
         return fail(c, AH_E_INVALID, "unknown kernel %d", kernel);
-    if (tile_y < 0 || tile_y > 16 || chunk_z < 0)
-        return fail(c, AH_E_INVALID, "tile_y must be in 0..16 and chunk_z >= 0");
+    if (chunk_z < 0 || (tile_y != 0 && !tiled_ty_valid(c->prec == AH_FP64, tile_y)))
+        return fail(c, AH_E_INVALID, "tile_y must be 0, 2, 4, 8 (or 16 for FP32); chunk_z >= 0");
     if (kernel == AH_KERNEL_TILED && !tiled_ok(c))
         return fail(c, AH_E_INVALID, "tiled kernel needs nx %% 64 == 0");
     c->kernel = kernel;

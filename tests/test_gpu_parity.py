@@ -244,3 +244,26 @@ def test_fused_schedule_matches_separate_measure(O):
     assert [o[0].step for o in obs] == [5, 10]
     for (g,), m in zip(obs, (m5, m10)):
         assert g.n_wind == m.n_wind and g.energy == pytest.approx(m.energy, rel=1e-13)
+
+
+@pytest.mark.parametrize("prec", [AH.AH_FP64, AH.AH_FP32])
+def test_tiling_invariance_is_bitwise(prec):
+    """Race and halo detector: the tiled kernel under different tile heights
+    and z-chunks (ragged in y and z, one chunk, one plane per chunk) gives
+    bit-identical fields after several steps."""
+    shape = (128, 20, 13)
+    _print_case(test="tiling", prec=prec, shape=shape)
+    tys = [2, 4, 8] + ([16] if prec == AH.AH_FP32 else [])
+    configs = [(ty, cz) for ty in tys for cz in (0, 1, 5, 13)]
+    p = AH.Params(*shape, precision=prec, tau0=1.0, tau_ref=3.0, era_p=1.0, s=1.0,
+                  init=AH.AH_INIT_NONE)
+    st = I.random_state(shape, seed=505)
+    ref = None
+    for ty, cz in configs:
+        with _ctx(p, upload(p, st), AH.AH_KERNEL_TILED, ty, cz) as c:
+            c.step(7)
+            got = c.fields().clone()
+        if ref is None:
+            ref = got
+        else:
+            assert torch.equal(got, ref), (ty, cz)
