@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-secondary", action="store_true", help="FP32 headline only")
     ap.add_argument("--kernel", default="auto", choices=["auto", "plain", "tiled"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy (reference for the "
+                         "HBM byte counters of a profiler run)")
     return ap.parse_args()
 
 
@@ -148,6 +151,29 @@ def main():
                               "steps": kp}
         line["speedup_fp32_vs_plain_fp64"] = rate32 / ratep
         line["speedup_fp64_vs_plain_fp64"] = rate64 / ratep
+    # reference: a plain 1 GiB device-to-device copy on this GPU (read + write)
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 4 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    line["roofline"]["copy_GBs"] = copy_gbs
+    line["roofline"]["frac_of_copy"] = achieved / copy_gbs
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = {"read": src.numel() * 4, "written": dst.numel() * 4}
+        del src, dst
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
