@@ -62,6 +62,13 @@ int fail(ah_ctx *c, int code, const char *fmt, ...) {
             return fail((ctx), AH_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));     \
     } while (0)
 
+#define TRY(x)                 \
+    do {                       \
+        int rc_ = (x);         \
+        if (rc_ != AH_OK)      \
+            return rc_;        \
+    } while (0)
+
 int grid_for(int64_t n, int threads, int cap) {
     int64_t b = (n + threads - 1) / threads;
     return (int)(b < cap ? (b < 1 ? 1 : b) : cap);
@@ -149,29 +156,21 @@ bool tiled_ok(const ah_ctx *c) {
     return true;
 }
 
-int launch_step(ah_ctx *c, int r) {
+bool use_tiled(const ah_ctx *c, int r) {
+    return c->kernel == AH_KERNEL_TILED || (c->kernel == AH_KERNEL_AUTO && c->p[r].nx % 64 == 0);
+}
+
+int launch_tiled(ah_ctx *c, int r, int mode, Slot *slot, int8_t *wind) {
     const ah_params &q = c->p[r];
-    const int64_t N = (int64_t)q.nx * q.ny * q.nz;
-    const bool tiled = c->kernel == AH_KERNEL_TILED ||
-                       (c->kernel == AH_KERNEL_AUTO && q.nx % 64 == 0);
-    if (tiled) {
-        int rc = launch_step_tiled(c->prec == AH_FP64, c->d_desc, c->d_coef, r, q.nx, q.ny, q.nz,
-                                   c->tile_y, c->chunk_z, c->stream);
-        if (rc)
-            return fail(c, AH_E_HIP, "tiled step launch failed: %s",
-                        hipGetErrorString((hipError_t)rc));
-        return AH_OK;
-    }
-    dim3 grid((unsigned)((N + 255) / 256));
-    if (c->prec == AH_FP64)
-        hipLaunchKernelGGL(k_step_plain<double>, grid, dim3(256), 0, c->stream, c->d_desc, c->d_coef, r);
-    else
-        hipLaunchKernelGGL(k_step_plain<float>, grid, dim3(256), 0, c->stream, c->d_desc, c->d_coef, r);
-    HIP_TRY(c, hipGetLastError());
+    int rc = launch_step_tiled(c->prec == AH_FP64, mode, c->d_desc, c->d_coef, r, q.nx, q.ny, q.nz,
+                               c->tile_y, c->chunk_z, slot, wind, c->stream);
+    if (rc)
+        return fail(c, AH_E_HIP, "tiled kernel launch (mode %d) failed: %s", mode,
+                    hipGetErrorString((hipError_t)rc));
     return AH_OK;
 }
 
-int launch_measure(ah_ctx *c, int r, Slot *slot, int8_t *wind) {
+int launch_measure_plain(ah_ctx *c, int r, Slot *slot, int8_t *wind) {
     const ah_params &q = c->p[r];
     const int64_t N = (int64_t)q.nx * q.ny * q.nz;
     dim3 grid(grid_for(N, kMeasureThreads, 4096));
@@ -183,6 +182,31 @@ int launch_measure(ah_ctx *c, int r, Slot *slot, int8_t *wind) {
                            c->d_desc, c->d_coef, r, slot, wind);
     HIP_TRY(c, hipGetLastError());
     return AH_OK;
+}
+
+// Advance realization r by one step (the coefficients are already on the
+// device); with slot != NULL also measure the state it reads into slot.
+int launch_step(ah_ctx *c, int r, Slot *slot) {
+    if (use_tiled(c, r))
+        return launch_tiled(c, r, slot ? MODE_STEP_MEASURE : MODE_STEP, slot, nullptr);
+    if (slot)
+        TRY(launch_measure_plain(c, r, slot, nullptr));
+    const ah_params &q = c->p[r];
+    const int64_t N = (int64_t)q.nx * q.ny * q.nz;
+    dim3 grid((unsigned)((N + 255) / 256));
+    if (c->prec == AH_FP64)
+        hipLaunchKernelGGL(k_step_plain<double>, grid, dim3(256), 0, c->stream, c->d_desc, c->d_coef, r);
+    else
+        hipLaunchKernelGGL(k_step_plain<float>, grid, dim3(256), 0, c->stream, c->d_desc, c->d_coef, r);
+    HIP_TRY(c, hipGetLastError());
+    return AH_OK;
+}
+
+// Measure the current state of realization r into slot (standalone pass).
+int launch_measure(ah_ctx *c, int r, Slot *slot, int8_t *wind) {
+    if (use_tiled(c, r))
+        return launch_tiled(c, r, MODE_MEASURE, slot, wind);
+    return launch_measure_plain(c, r, slot, wind);
 }
 
 int launch_finalize(ah_ctx *c, int64_t nslots) {
@@ -204,12 +228,6 @@ void release(ah_ctx *c) {
 
 } // namespace
 
-#define TRY(x)                 \
-    do {                       \
-        int rc_ = (x);         \
-        if (rc_ != AH_OK)      \
-            return rc_;        \
-    } while (0)
 
 extern "C" {
 
@@ -359,21 +377,18 @@ int ah_step(ah_ctx *c, int64_t nsteps, int32_t measure_every, ah_obs *out, int64
 
     size_t next = 0;
     for (int64_t i = 0; i < nsteps; ++i) {
-        if (next < meas.size() && meas_at[next] == i) {
-            TRY(launch_bookkeep(c, 0));
-            for (int r = 0; r < c->nreal; ++r)
-                if (meas[next][r])
-                    TRY(launch_measure(c, r, c->d_slots + next * c->nreal + r, nullptr));
-            ++next;
-        }
+        const bool measuring = next < meas.size() && meas_at[next] == i;
         TRY(launch_bookkeep(c, 1));
         for (int r = 0; r < c->nreal; ++r) {
             const ah_params &q = c->p[r];
             if (q.n_end > 0 && c->step[r] >= q.n_end)
                 continue;
-            TRY(launch_step(c, r));
+            Slot *slot = measuring && meas[next][r] ? c->d_slots + next * c->nreal + r : nullptr;
+            TRY(launch_step(c, r, slot));
             ++c->step[r];
         }
+        if (measuring)
+            ++next;
     }
 
     if (measure_every > 0) {

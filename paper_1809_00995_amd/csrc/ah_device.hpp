@@ -97,4 +97,41 @@ template <typename V> __device__ __forceinline__ V wave_max(V v) {
     return v;
 }
 
+// Block-wide sum of NV doubles and NC 64-bit integers over a block of NW
+// wavefronts, then one atomic per value into acc_s / acc_c.  Every thread of
+// the block must call it.
+template <int NV, int NC, int NW>
+__device__ __forceinline__ void block_accumulate(double (&v)[NV], unsigned long long (&cnt)[NC],
+                                                 double *acc_s, unsigned long long *acc_c) {
+    static_assert(NV + NC <= 64 * NW, "block too small for the reduction");
+    __shared__ double sv[NW][NV];
+    __shared__ unsigned long long sc[NW][NC];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double t = wave_sum(v[k]);
+        if (lane == 0)
+            sv[wave][k] = t;
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        unsigned long long t = wave_sum(cnt[k]);
+        if (lane == 0)
+            sc[wave][k] = t;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < NV) {
+        double s = 0.0;
+        for (int w = 0; w < NW; ++w)
+            s += sv[w][t];
+        unsafeAtomicAdd(acc_s + t, s);
+    } else if (t < NV + NC) {
+        unsigned long long s = 0;
+        for (int w = 0; w < NW; ++w)
+            s += sc[w][t - NV];
+        atomicAdd(acc_c + (t - NV), s);
+    }
+}
+
 } // namespace ah

@@ -19,41 +19,6 @@ __device__ __forceinline__ double wrap_pi(double u) {
     return u - kTwoPi * floor((u + kPi) / kTwoPi);
 }
 
-// Block-wide sum of NV doubles and NC 64-bit integers, then one atomic per
-// value into acc.  Every thread of the block must call it.
-template <int NV, int NC>
-__device__ __forceinline__ void block_accumulate(double (&v)[NV], unsigned long long (&cnt)[NC],
-                                                 double *acc_s, unsigned long long *acc_c) {
-    __shared__ double sv[kWaves][NV];
-    __shared__ unsigned long long sc[kWaves][NC];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        double t = wave_sum(v[k]);
-        if (lane == 0)
-            sv[wave][k] = t;
-    }
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-        unsigned long long t = wave_sum(cnt[k]);
-        if (lane == 0)
-            sc[wave][k] = t;
-    }
-    __syncthreads();
-    const int t = threadIdx.x;
-    if (t < NV) {
-        double s = 0.0;
-        for (int w = 0; w < kWaves; ++w)
-            s += sv[w][t];
-        unsafeAtomicAdd(acc_s + t, s);
-    } else if (t < NV + NC) {
-        unsigned long long s = 0;
-        for (int w = 0; w < kWaves; ++w)
-            s += sc[w][t - NV];
-        atomicAdd(acc_c + (t - NV), s);
-    }
-}
-
 // Per-site diagnostics of S_n, summed into acc.  wind (optional) receives W
 // of the xy, yz and zx plaquettes at each site (3 int8 planes).
 //   K = |Pi|^2, G = dx^-2 sum_i |e^{iA_i^x} phi^{x+i} - phi^x|^2, EE = dx^-2 sum_i E_i^2,
@@ -182,7 +147,7 @@ k_measure_plain(const RealDesc *descs, const Coef *coefs, int r, Slot *slot, int
         slot->c = c;
         slot->measured = 1;
     }
-    block_accumulate<A_COUNT, C_COUNT>(v, cnt, slot->acc.s, slot->acc.c);
+    block_accumulate<A_COUNT, C_COUNT, kWaves>(v, cnt, slot->acc.s, slot->acc.c);
 }
 
 // Gauss-law residual of S_n:

@@ -1,4 +1,5 @@
-// k_step_tiled.hpp -- the tiled step kernel for gfx950.
+// k_step_tiled.hpp -- the tiled step kernel for gfx950, with the network
+// diagnostics fused in.
 //
 // Same update as k_step_plain (Sec. 2, Eqs. (4)-(7)), organised for the
 // memory system:
@@ -17,11 +18,22 @@
 //  - Workgroups are dispatched round-robin over the 8 XCDs; tile numbers are
 //    remapped so each XCD walks a contiguous run of neighbouring tiles and
 //    the halo reads of adjacent tiles meet in the same L2.
+//
+// Modes: MODE_STEP advances S_n -> S_{n+1}; MODE_STEP_MEASURE also measures
+// S_n (the state it reads) on the way; MODE_MEASURE only measures (and can
+// write the per-plaquette winding map).  The measuring modes stage arg(phi)
+// in FP64 and the raw link angles A_i next to the phasors, and count the
+// winding of each plaquette from the wrap counts of its four links:
+// with m_i(s) = floor((theta(s+i) - theta(s) + A_i(s) + pi) / 2 pi) the
+// [.]_pi of Eq. (11) subtracts 2 pi m_i, the phase differences cancel around
+// the plaquette, and W_ij = -(m_i(x) + m_j(x+i) - m_i(x+j) - m_j(x)) exactly.
 #pragma once
 
 #include "ah_device.hpp"
 
 namespace ah {
+
+enum : int { MODE_STEP = 0, MODE_STEP_MEASURE = 1, MODE_MEASURE = 2 };
 
 // quantities staged per site in LDS
 enum : int { Q_PR, Q_PI, Q_UXC, Q_UXS, Q_UYC, Q_UYS, Q_UZC, Q_UZS, Q_COUNT };
@@ -57,8 +69,24 @@ __device__ __forceinline__ T plaq_sin(T aic, T ais, T bjc, T bjs, T cic, T cis, 
     return wr * vi + wi * vr;
 }
 
+// 1 - cos Xi_ij(s) = |conj(w) - v|^2 / 2 with w, v as in plaq_sin (|w v| = 1);
+// this form keeps its relative accuracy for small Xi.
+template <typename T>
+__device__ __forceinline__ T plaq_omc(T aic, T ais, T bjc, T bjs, T cic, T cis, T djc, T djs) {
+    const T wr = aic * djc + ais * djs, wi = ais * djc - aic * djs;
+    const T vr = bjc * cic + bjs * cis, vi = bjs * cic - bjc * cis;
+    const T a = wr - vr, b = wi + vi;
+    return (T)0.5 * (a * a + b * b);
+}
+
+// wrap count of a link: [u]_pi = u - 2 pi m (Eq. (11)), computed in FP64
+__device__ __forceinline__ long long wrap_count(double u) {
+    return (long long)floor((u + kPi) / kTwoPi);
+}
+
 template <typename T> struct SiteV {
     T pr, pm, ax, ay, az, uxc, uxs, uyc, uys, uzc, uzs;
+    double th;
 };
 
 __device__ __forceinline__ int wrap_mod(int v, int n) {
@@ -66,15 +94,20 @@ __device__ __forceinline__ int wrap_mod(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
-template <typename T, int TY>
+template <typename T, int TY, int MODE>
 __global__ void __launch_bounds__(64 * TY)
-k_step_tiled(const RealDesc *descs, const Coef *coefs, int r, int cz) {
+k_step_tiled(const RealDesc *descs, const Coef *coefs, int r, int cz, Slot *slot, int8_t *wind) {
+    constexpr bool MEAS = MODE != MODE_STEP;
+    constexpr bool UPD = MODE != MODE_MEASURE;
     using G = TileGeom<TY>;
+    constexpr int SM = MEAS ? G::S : 1;
     __shared__ T lds[2][Q_COUNT][G::S];
+    __shared__ double lth[2][SM];      // arg phi (measuring modes)
+    __shared__ T lar[2][3][SM];        // raw link angles (measuring modes)
 
     const RealDesc d = descs[r];
     const Coef c = coefs[r];
-    if (!c.active)
+    if (UPD && !c.active)
         return;
     const int nx = d.nx, ny = d.ny, nz = d.nz;
     const int ntx = nx >> 6, nty = (ny + TY - 1) / TY;
@@ -112,6 +145,21 @@ k_step_tiled(const RealDesc *descs, const Coef *coefs, int r, int cz) {
     const T d1 = (T)c.d1, d2 = (T)c.d2, d3 = (T)c.d3;
     const T dt = (T)d.dt, s2 = (T)(d.sigma * d.sigma);
 
+    // measurement constants and per-thread FP64 accumulators
+    double msum[A_COUNT];
+    unsigned long long mcnt[C_COUNT];
+    double ma2 = 0.0, mg = 0.0, mh = 0.0, idx2 = 0.0;
+    if (MEAS) {
+        for (int k = 0; k < A_COUNT; ++k)
+            msum[k] = 0.0;
+        for (int k = 0; k < C_COUNT; ++k)
+            mcnt[k] = 0ull;
+        ma2 = c.a_0 * c.a_0;
+        mg = pow(c.a_0, 2.0 * (1.0 - d.s)) / (2.0 * d.e0 * d.e0);
+        mh = d.lambda0 * pow(c.a_0, 2.0 + 2.0 * d.s);
+        idx2 = 1.0 / (d.dx * d.dx);
+    }
+
     auto load_site = [&](int s, SiteV<T> &v) {
         v.pr = phr[s];
         v.pm = phi[s];
@@ -121,6 +169,8 @@ k_step_tiled(const RealDesc *descs, const Coef *coefs, int r, int cz) {
         sincos_t(v.ax, &v.uxs, &v.uxc);
         sincos_t(v.ay, &v.uys, &v.uyc);
         sincos_t(v.az, &v.uzs, &v.uzc);
+        if (MEAS)
+            v.th = atan2((double)v.pm, (double)v.pr);
     };
     auto put = [&](int bf, int k, const SiteV<T> &v) {
         lds[bf][Q_PR][k] = v.pr;
@@ -131,6 +181,12 @@ k_step_tiled(const RealDesc *descs, const Coef *coefs, int r, int cz) {
         lds[bf][Q_UYS][k] = v.uys;
         lds[bf][Q_UZC][k] = v.uzc;
         lds[bf][Q_UZS][k] = v.uzs;
+        if (MEAS) {
+            lth[bf][k] = v.th;
+            lar[bf][0][k] = v.ax;
+            lar[bf][1][k] = v.ay;
+            lar[bf][2][k] = v.az;
+        }
     };
     auto stage_halo = [&](int bf, int z) {
         for (int h = t; h < G::HALO; h += 64 * TY) {
@@ -204,44 +260,119 @@ k_step_tiled(const RealDesc *descs, const Coef *coefs, int r, int cz) {
         const T pzx = plaq_sin(cur.uzc, cur.uzs, nxt.uxc, nxt.uxs, uzc_xp, uzs_xp, cur.uxc, cur.uxs);
         const T pzx_xm = plaq_sin(uzc_xm, uzs_xm, uxc_xmzp, uxs_xmzp, cur.uzc, cur.uzs, uxc_xm, uxs_xm);
 
-        // Eq. (4): sum_j [U_j(x) phi(x+j) + conj(U_j(x-j)) phi(x-j)] - 6 phi
         const T pr = cur.pr, pm = cur.pm;
-        T lr = (T)-6 * pr, lim = (T)-6 * pm;
-        lr += cur.uxc * pr_xp - cur.uxs * pi_xp + uxc_xm * pr_xm + uxs_xm * pi_xm;
-        lim += cur.uxc * pi_xp + cur.uxs * pr_xp + uxc_xm * pi_xm - uxs_xm * pr_xm;
-        lr += cur.uyc * pr_yp - cur.uys * pi_yp + uyc_ym * pr_ym + uys_ym * pi_ym;
-        lim += cur.uyc * pi_yp + cur.uys * pr_yp + uyc_ym * pi_ym - uys_ym * pr_ym;
-        lr += cur.uzc * nxt.pr - cur.uzs * nxt.pm + uzc_m * phr_m + uzs_m * phi_m;
-        lim += cur.uzc * nxt.pm + cur.uzs * nxt.pr + uzc_m * phi_m - uzs_m * phr_m;
-        const T v = pr * pr + pm * pm - s2;
-        const T pnr = c1 * pr0 + c2 * lr - c3 * v * pr;
-        const T pni = c1 * pi0 + c2 * lim - c3 * v * pm;
+        if (UPD) {
+            // Eq. (4): sum_j [U_j(x) phi(x+j) + conj(U_j(x-j)) phi(x-j)] - 6 phi
+            T lr = (T)-6 * pr, lim = (T)-6 * pm;
+            lr += cur.uxc * pr_xp - cur.uxs * pi_xp + uxc_xm * pr_xm + uxs_xm * pi_xm;
+            lim += cur.uxc * pi_xp + cur.uxs * pr_xp + uxc_xm * pi_xm - uxs_xm * pr_xm;
+            lr += cur.uyc * pr_yp - cur.uys * pi_yp + uyc_ym * pr_ym + uys_ym * pi_ym;
+            lim += cur.uyc * pi_yp + cur.uys * pr_yp + uyc_ym * pi_ym - uys_ym * pr_ym;
+            lr += cur.uzc * nxt.pr - cur.uzs * nxt.pm + uzc_m * phr_m + uzs_m * phi_m;
+            lim += cur.uzc * nxt.pm + cur.uzs * nxt.pr + uzc_m * phi_m - uzs_m * phr_m;
+            const T v = pr * pr + pm * pm - s2;
+            const T pnr = c1 * pr0 + c2 * lr - c3 * v * pr;
+            const T pni = c1 * pi0 + c2 * lim - c3 * v * pm;
 
-        // Eq. (5): current Im[conj(phi(x+i)) conj(U_i) phi(x)] and the curl
-        const T wxr = cur.uxc * pr + cur.uxs * pm, wxi = cur.uxc * pm - cur.uxs * pr;
-        const T wyr = cur.uyc * pr + cur.uys * pm, wyi = cur.uyc * pm - cur.uys * pr;
-        const T wzr = cur.uzc * pr + cur.uzs * pm, wzi = cur.uzc * pm - cur.uzs * pr;
-        const T jx = pr_xp * wxi - pi_xp * wxr;
-        const T jy = pr_yp * wyi - pi_yp * wyr;
-        const T jz = nxt.pr * wzi - nxt.pm * wzr;
-        const T curl_x = (pxy - pxy_ym) - (pzx - pzx_m);
-        const T curl_y = (pyz - pyz_m) - (pxy - pxy_xm);
-        const T curl_z = (pzx - pzx_xm) - (pyz - pyz_ym);
-        const T enx = d1 * ex0 + d3 * jx - d2 * curl_x;
-        const T eny = d1 * ey0 + d3 * jy - d2 * curl_y;
-        const T enz = d1 * ez0 + d3 * jz - d2 * curl_z;
+            // Eq. (5): current Im[conj(phi(x+i)) conj(U_i) phi(x)] and the curl
+            const T wxr = cur.uxc * pr + cur.uxs * pm, wxi = cur.uxc * pm - cur.uxs * pr;
+            const T wyr = cur.uyc * pr + cur.uys * pm, wyi = cur.uyc * pm - cur.uys * pr;
+            const T wzr = cur.uzc * pr + cur.uzs * pm, wzi = cur.uzc * pm - cur.uzs * pr;
+            const T jx = pr_xp * wxi - pi_xp * wxr;
+            const T jy = pr_yp * wyi - pi_yp * wyr;
+            const T jz = nxt.pr * wzi - nxt.pm * wzr;
+            const T curl_x = (pxy - pxy_ym) - (pzx - pzx_m);
+            const T curl_y = (pyz - pyz_m) - (pxy - pxy_xm);
+            const T curl_z = (pzx - pzx_xm) - (pyz - pyz_ym);
+            const T enx = d1 * ex0 + d3 * jx - d2 * curl_x;
+            const T eny = d1 * ey0 + d3 * jy - d2 * curl_y;
+            const T enz = d1 * ez0 + d3 * jz - d2 * curl_z;
 
-        if (owner) {
-            pir[s] = pnr;
-            pii[s] = pni;
-            E0[s] = enx;
-            E1[s] = eny;
-            E2[s] = enz;
-            ophr[s] = pr + dt * pnr;          // Eq. (6)
-            ophi[s] = pm + dt * pni;
-            oA0[s] = cur.ax + dt * enx;       // Eq. (7)
-            oA1[s] = cur.ay + dt * eny;
-            oA2[s] = cur.az + dt * enz;
+            if (owner) {
+                pir[s] = pnr;
+                pii[s] = pni;
+                E0[s] = enx;
+                E1[s] = eny;
+                E2[s] = enz;
+                ophr[s] = pr + dt * pnr;          // Eq. (6)
+                ophi[s] = pm + dt * pni;
+                oA0[s] = cur.ax + dt * enx;       // Eq. (7)
+                oA1[s] = cur.ay + dt * eny;
+                oA2[s] = cur.az + dt * enz;
+            }
+        }
+
+        if (MEAS && owner) {
+            // Eqs. (9)-(11) for the site of S_n read above
+            const bool finite = isfinite((double)pr) && isfinite((double)pm) &&
+                                isfinite((double)pr0) && isfinite((double)pi0) &&
+                                isfinite((double)cur.ax) && isfinite((double)cur.ay) &&
+                                isfinite((double)cur.az) && isfinite((double)ex0) &&
+                                isfinite((double)ey0) && isfinite((double)ez0);
+            long long w3[3] = { 0, 0, 0 };
+            if (!finite) {
+                mcnt[C_NONFIN] += 1ull;
+            } else {
+                const T gxr = cur.uxc * pr_xp - cur.uxs * pi_xp - pr;
+                const T gxi = cur.uxc * pi_xp + cur.uxs * pr_xp - pm;
+                const T gyr = cur.uyc * pr_yp - cur.uys * pi_yp - pr;
+                const T gyi = cur.uyc * pi_yp + cur.uys * pr_yp - pm;
+                const T gzr = cur.uzc * nxt.pr - cur.uzs * nxt.pm - pr;
+                const T gzi = cur.uzc * nxt.pm + cur.uzs * nxt.pr - pm;
+                const double K = (double)pr0 * pr0 + (double)pi0 * pi0;
+                const double Gr = idx2 * ((double)gxr * gxr + (double)gxi * gxi + (double)gyr * gyr +
+                                          (double)gyi * gyi + (double)gzr * gzr + (double)gzi * gzi);
+                const double EE = idx2 * ((double)ex0 * ex0 + (double)ey0 * ey0 + (double)ez0 * ez0);
+                const T oxy = plaq_omc(cur.uxc, cur.uxs, uyc_xp, uys_xp, uxc_yp, uxs_yp, cur.uyc, cur.uys);
+                const T oyz = plaq_omc(cur.uyc, cur.uys, uzc_yp, uzs_yp, nxt.uyc, nxt.uys, cur.uzc, cur.uzs);
+                const T ozx = plaq_omc(cur.uzc, cur.uzs, nxt.uxc, nxt.uxs, uzc_xp, uzs_xp, cur.uxc, cur.uxs);
+                const double BB = 2.0 * idx2 * idx2 * ((double)oxy + (double)oyz + (double)ozx);
+                const double vv = (double)pr * pr + (double)pm * pm - (double)s2;
+                const double V = 0.25 * vv * vv;
+                const double lag = ma2 * K - ma2 * Gr + mg * (EE - BB) - mh * V;
+                const double rho = ma2 * K + ma2 * Gr + mg * (EE + BB) + mh * V;
+                msum[A_KIN] += ma2 * K;
+                msum[A_GRAD] += ma2 * Gr;
+                msum[A_ELEC] += mg * EE;
+                msum[A_MAG] += mg * BB;
+                msum[A_POT] += mh * V;
+                msum[A_LAG] += lag;
+                msum[A_NUM_L] += K * lag;
+                msum[A_NUM_V] += K * V;
+                msum[A_NUM_R] += K * rho;
+                msum[A_DEN_L] += Gr * lag;
+                msum[A_DEN_V] += Gr * V;
+                msum[A_DEN_R] += Gr * rho;
+
+                // winding (Eq. (11)) from link wrap counts
+                const double t0 = cur.th, t_xp = lth[cb][q + 1], t_yp = lth[cb][q + G::W];
+                const double t_xpyp = lth[cb][q + 1 + G::W];
+                const double t_zp = nxt.th, t_xpzp = lth[nb_][q + 1], t_ypzp = lth[nb_][q + G::W];
+                const double ax = cur.ax, ay = cur.ay, az = cur.az;
+                const double ay_xp = lar[cb][1][q + 1], az_xp = lar[cb][2][q + 1];
+                const double ax_yp = lar[cb][0][q + G::W], az_yp = lar[cb][2][q + G::W];
+                const double ax_zp = nxt.ax, ay_zp = nxt.ay;
+                const long long mx = wrap_count(t_xp - t0 + ax);
+                const long long my = wrap_count(t_yp - t0 + ay);
+                const long long mz = wrap_count(t_zp - t0 + az);
+                const long long my_xp = wrap_count(t_xpyp - t_xp + ay_xp);
+                const long long mx_yp = wrap_count(t_xpyp - t_yp + ax_yp);
+                const long long mz_yp = wrap_count(t_ypzp - t_yp + az_yp);
+                const long long my_zp = wrap_count(t_ypzp - t_zp + ay_zp);
+                const long long mx_zp = wrap_count(t_xpzp - t_zp + ax_zp);
+                const long long mz_xp = wrap_count(t_xpzp - t_xp + az_xp);
+                w3[0] = -(mx + my_xp - mx_yp - my);
+                w3[1] = -(my + mz_yp - my_zp - mz);
+                w3[2] = -(mz + mx_zp - mz_xp - mx);
+                for (int k = 0; k < 3; ++k) {
+                    mcnt[C_W0 + k] += (unsigned long long)w3[k];
+                    mcnt[C_N0 + k] += (unsigned long long)(w3[k] < 0 ? -w3[k] : w3[k]);
+                    mcnt[C_PIERCED] += w3[k] != 0 ? 1ull : 0ull;
+                }
+            }
+            if (MODE == MODE_MEASURE && wind)
+                for (int k = 0; k < 3; ++k)
+                    wind[(size_t)k * (size_t)d.N + s] = (int8_t)w3[k];
         }
 
         phr_m = pr;
@@ -252,6 +383,14 @@ k_step_tiled(const RealDesc *descs, const Coef *coefs, int r, int cz) {
         pzx_m = pzx;
         cur = nxt;
         __syncthreads();
+    }
+
+    if (MEAS) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            slot->c = c;
+            slot->measured = 1;
+        }
+        block_accumulate<A_COUNT, C_COUNT, TY>(msum, mcnt, slot->acc.s, slot->acc.c);
     }
 }
 
@@ -271,13 +410,36 @@ inline void tiled_defaults(bool fp64, int nx, int ny, int nz, int &ty, int &cz) 
     }
 }
 
-template <typename T, int TY>
+template <typename T, int TY, int MODE>
 hipError_t launch_tiled_ty(const RealDesc *desc, const Coef *coef, int r, int nx, int ny, int nz,
-                           int cz, hipStream_t stream) {
+                           int cz, Slot *slot, int8_t *wind, hipStream_t stream) {
     const long blocks = (long)(nx / 64) * ((ny + TY - 1) / TY) * ((nz + cz - 1) / cz);
-    hipLaunchKernelGGL((k_step_tiled<T, TY>), dim3((unsigned)blocks), dim3(64 * TY), 0, stream,
-                       desc, coef, r, cz);
+    hipLaunchKernelGGL((k_step_tiled<T, TY, MODE>), dim3((unsigned)blocks), dim3(64 * TY), 0,
+                       stream, desc, coef, r, cz, slot, wind);
     return hipGetLastError();
+}
+
+template <typename T, int MODE>
+hipError_t launch_tiled_mode(int ty, const RealDesc *desc, const Coef *coef, int r, int nx, int ny,
+                             int nz, int cz, Slot *slot, int8_t *wind, hipStream_t stream) {
+    // The measuring modes hold ~220 VGPRs: keep them at tiles that do not
+    // spill (FP32 <= 8 rows, FP64 <= 4).  The update is the same arithmetic
+    // for every tile height, so this only changes the order of the sums.
+    constexpr bool MEAS = MODE != MODE_STEP;
+    constexpr int TYMAX = MEAS ? (sizeof(T) == 4 ? 8 : 4) : (sizeof(T) == 4 ? 16 : 8);
+    if (ty > TYMAX)
+        ty = TYMAX;
+    switch (ty) {
+    case 2: return launch_tiled_ty<T, 2, MODE>(desc, coef, r, nx, ny, nz, cz, slot, wind, stream);
+    case 4: return launch_tiled_ty<T, 4, MODE>(desc, coef, r, nx, ny, nz, cz, slot, wind, stream);
+    default:
+        if constexpr (TYMAX >= 16)
+            if (ty == 16)
+                return launch_tiled_ty<T, 16, MODE>(desc, coef, r, nx, ny, nz, cz, slot, wind, stream);
+        if constexpr (TYMAX >= 8)
+            return launch_tiled_ty<T, 8, MODE>(desc, coef, r, nx, ny, nz, cz, slot, wind, stream);
+        return hipErrorInvalidValue;
+    }
 }
 
 // Valid tile heights: FP32 2, 4, 8, 16; FP64 2, 4, 8.
@@ -285,26 +447,23 @@ inline bool tiled_ty_valid(bool fp64, int ty) {
     return ty == 2 || ty == 4 || ty == 8 || (!fp64 && ty == 16);
 }
 
-inline int launch_step_tiled(bool fp64, const RealDesc *desc, const Coef *coef, int r, int nx,
-                             int ny, int nz, int tile_y, int chunk_z, hipStream_t stream) {
+// Launch one tiled kernel (mode MODE_*) for realization r.
+inline int launch_step_tiled(bool fp64, int mode, const RealDesc *desc, const Coef *coef, int r,
+                             int nx, int ny, int nz, int tile_y, int chunk_z, Slot *slot,
+                             int8_t *wind, hipStream_t stream) {
     int ty = tile_y, cz = chunk_z;
     tiled_defaults(fp64, nx, ny, nz, ty, cz);
     if (nx % 64 != 0 || !tiled_ty_valid(fp64, ty) || cz < 1)
         return (int)hipErrorInvalidValue;
     hipError_t e;
     if (fp64) {
-        switch (ty) {
-        case 2: e = launch_tiled_ty<double, 2>(desc, coef, r, nx, ny, nz, cz, stream); break;
-        case 4: e = launch_tiled_ty<double, 4>(desc, coef, r, nx, ny, nz, cz, stream); break;
-        default: e = launch_tiled_ty<double, 8>(desc, coef, r, nx, ny, nz, cz, stream); break;
-        }
+        e = mode == MODE_STEP ? launch_tiled_mode<double, MODE_STEP>(ty, desc, coef, r, nx, ny, nz, cz, slot, wind, stream)
+          : mode == MODE_STEP_MEASURE ? launch_tiled_mode<double, MODE_STEP_MEASURE>(ty, desc, coef, r, nx, ny, nz, cz, slot, wind, stream)
+          : launch_tiled_mode<double, MODE_MEASURE>(ty, desc, coef, r, nx, ny, nz, cz, slot, wind, stream);
     } else {
-        switch (ty) {
-        case 2: e = launch_tiled_ty<float, 2>(desc, coef, r, nx, ny, nz, cz, stream); break;
-        case 4: e = launch_tiled_ty<float, 4>(desc, coef, r, nx, ny, nz, cz, stream); break;
-        case 8: e = launch_tiled_ty<float, 8>(desc, coef, r, nx, ny, nz, cz, stream); break;
-        default: e = launch_tiled_ty<float, 16>(desc, coef, r, nx, ny, nz, cz, stream); break;
-        }
+        e = mode == MODE_STEP ? launch_tiled_mode<float, MODE_STEP>(ty, desc, coef, r, nx, ny, nz, cz, slot, wind, stream)
+          : mode == MODE_STEP_MEASURE ? launch_tiled_mode<float, MODE_STEP_MEASURE>(ty, desc, coef, r, nx, ny, nz, cz, slot, wind, stream)
+          : launch_tiled_mode<float, MODE_MEASURE>(ty, desc, coef, r, nx, ny, nz, cz, slot, wind, stream);
     }
     return (int)e;
 }

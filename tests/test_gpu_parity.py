@@ -126,18 +126,19 @@ def test_config_32cubed_fp64_run(O):
     assert max(group_errors(got, st).values()) < 1e-10
 
 
+@pytest.mark.parametrize("kernel", KERNELS, ids=["plain", "tiled"])
 @pytest.mark.parametrize("prec", [AH.AH_FP64, AH.AH_FP32])
-def test_measure_and_wind_map_match_oracle(O, prec):
+def test_measure_and_wind_map_match_oracle(O, prec, kernel):
     """Standalone measurement of a generic state, and the winding map plaquette
     by plaquette on identical input fields."""
     shape = (64, 10, 9)
-    _print_case(test="measure", prec=prec)
+    _print_case(test="measure", prec=prec, kernel=kernel)
     p = AH.Params(*shape, precision=prec, tau0=3.0, tau_ref=4.0, era_p=2.0, s=0.0,
                   init=AH.AH_INIT_NONE, step0=7)
     st = I.random_state(shape, seed=303, amp_a=2.5)
     if prec == AH.AH_FP32:
         st = st.astype(np.float32).astype(np.float64)
-    with AH.Context([p], [upload(p, st)]) as c:
+    with _ctx(p, upload(p, st), kernel) as c:
         (g,), (w,) = c.measure(wind=True)
         w = w.cpu().numpy().astype(np.int64)
     o = O.measure(oracle_params(O, p), 7, st, wind_map=True)
@@ -145,10 +146,13 @@ def test_measure_and_wind_map_match_oracle(O, prec):
     allowed = plaquette_touches(ambiguous_links(st))
     assert not (diff & ~allowed).any()
     print("winding mismatches (all at ambiguous links):", int(diff.sum()))
+    # the plain kernel forms every density in FP64; the tiled kernel in the
+    # storage precision (FP32 rounding, ~1e-7 per term), accumulating in FP64
+    rel = 1e-6 if (prec == AH.AH_FP32 and kernel == AH.AH_KERNEL_TILED) else 1e-10
     if not diff.any():
-        _compare_obs(g, o, 1e-10)
+        _compare_obs(g, o, rel)
     else:
-        assert g.energy == pytest.approx(o.energy, rel=1e-10)
+        assert g.energy == pytest.approx(o.energy, rel=rel)
 
 
 @pytest.mark.parametrize("prec", [AH.AH_FP64, AH.AH_FP32])
@@ -267,3 +271,44 @@ def test_tiling_invariance_is_bitwise(prec):
             ref = got
         else:
             assert torch.equal(got, ref), (ty, cz)
+
+
+def test_fused_measurement_run_matches_oracle(O):
+    """FP64, 64x24x20, radiation s=1 from the random-phase start: 40 steps with
+    the diagnostics fused into the tiled step kernel every 10 steps."""
+    _print_case(test="fused_run")
+    p = AH.Params(64, 24, 20, precision=AH.AH_FP64, tau0=0.0, tau_ref=5.0, era_p=1.0, s=1.0,
+                  seed=11)
+    op = oracle_params(O, p)
+    with _ctx(p, AH.alloc_planes(p), AH.AH_KERNEL_TILED) as c:
+        obs = c.step(40, measure_every=10)
+        got = fields_np(c)
+    st, oobs = O.run(op, O.init_random_phase(op), 0, 40, measure_every=10)
+    assert [o[0].step for o in obs] == [0, 10, 20, 30]
+    for (g,), o in zip(obs, oobs):
+        _compare_obs(g, o, 1e-9)
+    assert max(group_errors(got, st).values()) < 1e-11
+
+
+@pytest.mark.parametrize("prec", [AH.AH_FP64, AH.AH_FP32])
+def test_fused_measurement_on_identical_input(O, prec):
+    """The fused FP32/FP64 measurement of a state against the oracle's
+    measurement of the same (widened) state."""
+    shape = (128, 12, 10)
+    _print_case(test="fused_identical", prec=prec)
+    p = AH.Params(*shape, precision=prec, tau0=1.0, tau_ref=3.0, era_p=2.0, s=0.0, seed=21)
+    with _ctx(p, AH.alloc_planes(p), AH.AH_KERNEL_TILED) as c:
+        c.step(10)
+        st = fields_np(c)
+        (g,), = c.step(1, measure_every=10)
+    o = O.measure(oracle_params(O, p), 10, st, wind_map=True)
+    rel = 1e-10 if prec == AH.AH_FP64 else 2e-5
+    assert g.step == 10
+    amb = plaquette_touches(ambiguous_links(st)).sum()
+    assert abs(g.n_wind - o.n_wind) <= amb
+    if amb == 0:
+        assert g.n_wind_dir == o.n_wind_dir
+    for k in ("kin", "grad", "elec", "mag", "pot", "energy", "sum_lag"):
+        assert getattr(g, k) == pytest.approx(getattr(o, k), rel=rel), k
+    for k in ("num", "den", "v2"):
+        assert np.allclose(getattr(g, k), getattr(o, k), rtol=rel * 10, atol=1e-20), k
