@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--n", type=int, default=N, help="lattice extent (default 512)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-secondary", action="store_true", help="FP32 headline only")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--kernel", default="auto", choices=["auto", "plain", "tiled"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for the "
@@ -86,6 +87,48 @@ def run_form(AH, torch, n, prec, kernel, steps, warmup):
     del planes
     torch.cuda.empty_cache()
     return rate, ms / steps, kms, last
+
+
+def ensemble_params(AH):
+    """48 x 128^3 + 16 x 64^3 + 4 x 256^3, FP32; realization r: radiation s=1 if r is even,
+    matter s=0 if odd; seed 1000 + r; each runs to its own tau_end = N dx / 2 (n_end)."""
+    ps = []
+    for n, count in ((256, 4), (128, 48), (64, 16)):
+        for _ in range(count):
+            r = len(ps)
+            rad = r % 2 == 0
+            tau_end = n * 0.5 / 2.0
+            ps.append(AH.Params(n, n, n, precision=AH.AH_FP32, dx=0.5, dt=0.1, tau0=0.0,
+                                tau_ref=tau_end, era_p=1.0 if rad else 2.0, s=1.0 if rad else 0.0,
+                                seed=1000 + r, n_end=int(round(tau_end / 0.1))))
+    return ps
+
+
+def run_ensemble(AH, torch, batched, graph_steps, tune):
+    """The whole ensemble to completion (640 steps), diagnostics every 20 steps.
+    Returns (total site-updates/s, seconds, tuning)."""
+    ps = ensemble_params(AH)
+    planes = [AH.alloc_planes(p) for p in ps]
+    ctx = AH.Context(ps, planes)
+    tuning = None
+    if tune:
+        tuning = ctx.autotune()
+    ctx.set_launch(batched, graph_steps)
+    ctx.step(1)                                  # first-launch costs outside the timing
+    torch.cuda.synchronize()
+    total = sum(p.sites * (p.n_end - 1) for p in ps)
+    stream = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    ctx.step(max(p.n_end for p in ps) - 1, measure_every=MEASURE_EVERY)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    sec = t0.elapsed_time(t1) * 1e-3
+    assert all(ctx.current_step(r) == p.n_end for r, p in enumerate(ps))
+    ctx.close()
+    del planes
+    torch.cuda.empty_cache()
+    return total / sec, sec, tuning
 
 
 def cpu_baseline():
@@ -151,6 +194,21 @@ def main():
                               "steps": kp}
         line["speedup_fp32_vs_plain_fp64"] = rate32 / ratep
         line["speedup_fp64_vs_plain_fp64"] = rate64 / ratep
+    if not args.no_secondary and not args.no_ensemble:
+        rb, sb, tuning = run_ensemble(AH, torch, True, 10, True)
+        rs, ss, _ = run_ensemble(AH, torch, False, 0, False)
+        print(f"# ensemble: batched+graph+tuned {rb:.4g} site-updates/s ({sb:.3f} s), "
+              f"per-realization launches {rs:.4g} ({ss:.3f} s)", file=sys.stderr, flush=True)
+        line["ensemble"] = {
+            "workload": "48 x 128^3 + 16 x 64^3 + 4 x 256^3 FP32, radiation s=1 / matter s=0 "
+                        "alternating, each to tau_end = N dx / 2 (320 / 160 / 640 steps), "
+                        f"diagnostics every {MEASURE_EVERY} steps",
+            "value": rb, "unit": "site-updates/s", "seconds": sb,
+            "frac": rb * BYTES_PER_SITE["f32"] / 1e9 / HBM_PEAK_GBS,
+            "launch": "one persistent launch per step, 10-step hipGraphs, autotuned tiles",
+            "tile_y": tuning[0] if tuning else None,
+            "per_realization_launches": {"value": rs, "seconds": ss},
+            "speedup_vs_per_realization": rb / rs}
     # reference: a plain 1 GiB device-to-device copy on this GPU (read + write)
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)

@@ -184,6 +184,32 @@ int ah_current_step(const ah_ctx *ctx, int32_t r, int64_t *n);
  */
 int ah_set_kernel(ah_ctx *ctx, int32_t kernel, int32_t tile_y, int32_t chunk_z);
 
+/*
+ * Launch strategy.  batched = 1: every step of all realizations is one
+ * launch of a persistent kernel that walks a work list of (realization,
+ * tile, z-chunk) items -- the ensemble form for many independent
+ * realizations of uneven size (Sec. 1 and Sec. 5 of the paper motivate
+ * thousands of runs); it needs nx % 64 == 0 and one common step0, and falls
+ * back to one launch per realization otherwise.  graph_steps = g > 0: runs
+ * of g unmeasured steps are captured once into a hipGraph (on a stream of
+ * the context, ordered after and before the caller's stream with events) and
+ * replayed; measuring steps are launched directly.  0, 0 is the default.
+ * Results are bit-identical to the default launch.
+ */
+int ah_set_launch(ah_ctx *ctx, int32_t batched, int32_t graph_steps);
+
+/*
+ * Autotuner: times the tiled step kernel for candidate tile heights and
+ * z-chunks on a scratch lattice of each distinct shape of the context (the
+ * caller's fields are not touched; scratch of up to 15 planes of
+ * nx*ny*min(nz,128) is allocated and freed), installs the tile height with
+ * the least estimated total time per step and the best z-chunk for each
+ * realization, and returns them in *tile_y and chunk_z[n_real] (either may be
+ * NULL).  Needs the tiled kernel (AH_E_STATE otherwise).  Synchronises the
+ * stream.
+ */
+int ah_autotune(ah_ctx *ctx, int32_t *tile_y, int32_t *chunk_z);
+
 /* Release the context's scratch (not the caller's planes).  NULL is a no-op. */
 int ah_free(ah_ctx *ctx);
 

@@ -25,7 +25,7 @@ AH_KERNEL_AUTO, AH_KERNEL_PLAIN, AH_KERNEL_TILED = 0, 1, 2
 FIELDS = ("phi_re", "phi_im", "pi_re", "pi_im", "ax", "ay", "az", "ex", "ey", "ez")
 EXPORTED = ("ah_error_string", "ah_last_error", "ah_init", "ah_step", "ah_measure",
             "ah_gauss_residual", "ah_current_planes", "ah_current_step", "ah_set_kernel",
-            "ah_free")
+            "ah_set_launch", "ah_autotune", "ah_free")
 
 
 class AHError(RuntimeError):
@@ -85,6 +85,8 @@ def load_library(path: str = LIB_PATH):
     lib.ah_current_planes.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32)]
     lib.ah_current_step.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64)]
     lib.ah_set_kernel.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
+    lib.ah_set_launch.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+    lib.ah_autotune.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32)]
     lib.ah_free.argtypes = [C.c_void_p]
     for name in EXPORTED:
         if name != "ah_error_string" and name != "ah_last_error":
@@ -260,6 +262,16 @@ class Context:
 
     def set_kernel(self, kernel: int, tile_y: int = 0, chunk_z: int = 0):
         _check(self.lib, self._ctx, self.lib.ah_set_kernel(self._ctx, kernel, tile_y, chunk_z))
+
+    def set_launch(self, batched: bool = False, graph_steps: int = 0):
+        _check(self.lib, self._ctx, self.lib.ah_set_launch(self._ctx, int(batched), graph_steps))
+
+    def autotune(self):
+        """Time tile heights and z-chunks on scratch lattices; returns (tile_y, [chunk_z])."""
+        ty = C.c_int32()
+        cz = (C.c_int32 * self.n_real)()
+        _check(self.lib, self._ctx, self.lib.ah_autotune(self._ctx, C.byref(ty), cz))
+        return ty.value, list(cz)
 
     def close(self):
         if self._ctx:

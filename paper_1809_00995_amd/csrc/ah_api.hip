@@ -1,8 +1,10 @@
 // ah_api.hip -- host side of the C ABI declared in include/ah.h: parameter
-// validation, the context's device scratch, and the launch sequence of each
-// entry point.  All GPU work of a context goes on its stream.
+// validation, the context's device scratch, the launch sequence of each entry
+// point, graph capture of step sequences, and the autotuner.  All GPU work of
+// a context is ordered on its stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -33,8 +35,21 @@ struct ah_ctx {
     ah_obs *d_obs = nullptr;
     int64_t slot_cap = 0;             // slots allocated, in states (x nreal)
     unsigned long long *d_gauss = nullptr;  // [nreal][2]
+    // launch configuration
     int kernel = AH_KERNEL_AUTO;
-    int tile_y = 0, chunk_z = 0;
+    int tile_y = 0;                   // 0: default
+    std::vector<int> cz;              // per-realization z-chunk, 0: default
+    int batched = 0;                  // 1: one persistent launch per step
+    int graph_steps = 0;              // > 0: replay runs of unmeasured steps from a graph
+    // batched work list (rebuilt when the configuration changes)
+    BatchItem *d_items = nullptr;
+    int n_items = 0, items_ty = 0, grid_step = 0, grid_meas = 0;
+    bool items_valid = false;
+    // graph replay
+    hipStream_t gstream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool gexec_valid = false;
     std::string err;
 };
 
@@ -73,6 +88,8 @@ int grid_for(int64_t n, int threads, int cap) {
     int64_t b = (n + threads - 1) / threads;
     return (int)(b < cap ? (b < 1 ? 1 : b) : cap);
 }
+
+int64_t sites_of(const ah_params &q) { return (int64_t)q.nx * q.ny * q.nz; }
 
 double scale_factor_host(const ah_params &p, double tau) {
     double t = tau > 0.0 ? tau : 0.0;
@@ -115,6 +132,18 @@ int validate(const ah_params &q, int r, const ah_buffers &b, int prec) {
     if (((uintptr_t)b.planes & 255u) != 0)
         return bad(AH_E_INVALID, "planes must be 256-byte aligned");
     return AH_OK;
+}
+
+bool frozen(const ah_ctx *c, int r) {
+    return c->p[r].n_end > 0 && c->step[r] >= c->p[r].n_end;
+}
+
+void invalidate_plans(ah_ctx *c) {
+    c->items_valid = false;
+    if (c->gexec)
+        (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->gexec_valid = false;
 }
 
 int ensure_slots(ah_ctx *c, int64_t states) {
@@ -160,10 +189,28 @@ bool use_tiled(const ah_ctx *c, int r) {
     return c->kernel == AH_KERNEL_TILED || (c->kernel == AH_KERNEL_AUTO && c->p[r].nx % 64 == 0);
 }
 
+// The batched kernel needs tiled shapes and one common step index (so every
+// realization measures at the same steps).
+bool batch_ok(const ah_ctx *c) {
+    if (!c->batched || c->kernel == AH_KERNEL_PLAIN || !tiled_ok(c))
+        return false;
+    for (const auto &q : c->p)
+        if (q.step0 != c->p[0].step0)
+            return false;
+    return true;
+}
+
+// Tile height of the batched kernel: it must serve the measuring mode too.
+int batch_ty(const ah_ctx *c) {
+    const bool fp64 = c->prec == AH_FP64;
+    int ty = c->tile_y > 0 ? c->tile_y : (fp64 ? 4 : 8);
+    return std::min(ty, tiled_ty_max(fp64, MODE_STEP_MEASURE));
+}
+
 int launch_tiled(ah_ctx *c, int r, int mode, Slot *slot, int8_t *wind) {
     const ah_params &q = c->p[r];
     int rc = launch_step_tiled(c->prec == AH_FP64, mode, c->d_desc, c->d_coef, r, q.nx, q.ny, q.nz,
-                               c->tile_y, c->chunk_z, slot, wind, c->stream);
+                               c->tile_y, c->cz[r], slot, wind, c->stream);
     if (rc)
         return fail(c, AH_E_HIP, "tiled kernel launch (mode %d) failed: %s", mode,
                     hipGetErrorString((hipError_t)rc));
@@ -171,8 +218,7 @@ int launch_tiled(ah_ctx *c, int r, int mode, Slot *slot, int8_t *wind) {
 }
 
 int launch_measure_plain(ah_ctx *c, int r, Slot *slot, int8_t *wind) {
-    const ah_params &q = c->p[r];
-    const int64_t N = (int64_t)q.nx * q.ny * q.nz;
+    const int64_t N = sites_of(c->p[r]);
     dim3 grid(grid_for(N, kMeasureThreads, 4096));
     if (c->prec == AH_FP64)
         hipLaunchKernelGGL(k_measure_plain<double>, grid, dim3(kMeasureThreads), 0, c->stream,
@@ -191,8 +237,7 @@ int launch_step(ah_ctx *c, int r, Slot *slot) {
         return launch_tiled(c, r, slot ? MODE_STEP_MEASURE : MODE_STEP, slot, nullptr);
     if (slot)
         TRY(launch_measure_plain(c, r, slot, nullptr));
-    const ah_params &q = c->p[r];
-    const int64_t N = (int64_t)q.nx * q.ny * q.nz;
+    const int64_t N = sites_of(c->p[r]);
     dim3 grid((unsigned)((N + 255) / 256));
     if (c->prec == AH_FP64)
         hipLaunchKernelGGL(k_step_plain<double>, grid, dim3(256), 0, c->stream, c->d_desc, c->d_coef, r);
@@ -216,10 +261,139 @@ int launch_finalize(ah_ctx *c, int64_t nslots) {
     return AH_OK;
 }
 
+// Work list of the batched kernel: the tiles of every realization, largest
+// realizations first, each realization's tiles in x-fastest order so that
+// neighbours are consecutive items.
+int build_items(ah_ctx *c) {
+    if (c->items_valid)
+        return AH_OK;
+    const bool fp64 = c->prec == AH_FP64;
+    const int ty = batch_ty(c);
+    std::vector<int> order(c->nreal);
+    for (int r = 0; r < c->nreal; ++r)
+        order[r] = r;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return sites_of(c->p[a]) > sites_of(c->p[b]); });
+    std::vector<BatchItem> items;
+    for (int r : order) {
+        const ah_params &q = c->p[r];
+        int t = ty, z = c->cz[r];
+        tiled_defaults(fp64, q.nx, q.ny, q.nz, t, z);
+        const int tiles = (q.nx / 64) * ((q.ny + ty - 1) / ty) * ((q.nz + z - 1) / z);
+        for (int k = 0; k < tiles; ++k)
+            items.push_back(BatchItem{ r, k, z, 0 });
+    }
+    if (c->d_items)
+        (void)hipFree(c->d_items);
+    c->d_items = nullptr;
+    HIP_TRY(c, hipMalloc(&c->d_items, items.size() * sizeof(BatchItem)));
+    HIP_TRY(c, hipMemcpyAsync(c->d_items, items.data(), items.size() * sizeof(BatchItem),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int rc = batch_dispatch(fp64, MODE_STEP, ty, nullptr, nullptr, nullptr, 0, nullptr, 0, nullptr,
+                            &c->grid_step);
+    if (rc == 0)
+        rc = batch_dispatch(fp64, MODE_STEP_MEASURE, ty, nullptr, nullptr, nullptr, 0, nullptr, 0,
+                            nullptr, &c->grid_meas);
+    if (rc)
+        return fail(c, AH_E_HIP, "occupancy query failed: %s", hipGetErrorString((hipError_t)rc));
+    c->n_items = (int)items.size();
+    c->items_ty = ty;
+    c->items_valid = true;
+    return AH_OK;
+}
+
+// One step of every realization: bookkeeping, then the batched kernel or one
+// launch per realization.  slots_row[r] receives the measurement of
+// realization r when want_meas[r] (slots_row == NULL: no measurement).  With
+// skip_frozen the host leaves out realizations that reached n_end (the device
+// skips them anyway, which keeps captured graphs valid).
+int launch_one_step(ah_ctx *c, Slot *slots_row, const char *want_meas, bool skip_frozen) {
+    TRY(launch_bookkeep(c, 1));
+    if (batch_ok(c)) {
+        TRY(build_items(c));
+        const int mode = slots_row ? MODE_STEP_MEASURE : MODE_STEP;
+        int rc = batch_dispatch(c->prec == AH_FP64, mode, c->items_ty, c->d_desc, c->d_coef,
+                                c->d_items, c->n_items, slots_row,
+                                slots_row ? c->grid_meas : c->grid_step, c->stream, nullptr);
+        if (rc)
+            return fail(c, AH_E_HIP, "batched kernel launch failed: %s",
+                        hipGetErrorString((hipError_t)rc));
+        return AH_OK;
+    }
+    for (int r = 0; r < c->nreal; ++r) {
+        if (skip_frozen && frozen(c, r))
+            continue;
+        Slot *slot = slots_row && want_meas[r] ? slots_row + r : nullptr;
+        TRY(launch_step(c, r, slot));
+    }
+    return AH_OK;
+}
+
+void advance_mirror(ah_ctx *c, int64_t k) {
+    for (int r = 0; r < c->nreal; ++r) {
+        const ah_params &q = c->p[r];
+        int64_t n = c->step[r] + k;
+        c->step[r] = (q.n_end > 0 && n > q.n_end) ? std::max(c->step[r], q.n_end) : n;
+    }
+}
+
+// Capture graph_steps unmeasured steps once (on the context's own stream)
+// and replay it reps times, ordered after the caller's stream work and
+// before anything the caller enqueues later.
+int run_graph(ah_ctx *c, int64_t reps) {
+    if (!c->gstream) {
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    }
+    if (batch_ok(c))
+        TRY(build_items(c));     // outside the capture: it copies and synchronises
+    if (!c->gexec_valid) {
+        hipStream_t user = c->stream;
+        HIP_TRY(c, hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+        c->stream = c->gstream;
+        int rc = AH_OK;
+        for (int k = 0; k < c->graph_steps && rc == AH_OK; ++k)
+            rc = launch_one_step(c, nullptr, nullptr, false);
+        c->stream = user;
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(c->gstream, &graph);
+        if (rc != AH_OK) {
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess)
+            return fail(c, AH_E_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess)
+            return fail(c, AH_E_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+        c->gexec_valid = true;
+    }
+    HIP_TRY(c, hipEventRecord(c->ev_in, c->stream));
+    HIP_TRY(c, hipStreamWaitEvent(c->gstream, c->ev_in, 0));
+    for (int64_t k = 0; k < reps; ++k)
+        HIP_TRY(c, hipGraphLaunch(c->gexec, c->gstream));
+    HIP_TRY(c, hipEventRecord(c->ev_out, c->gstream));
+    HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_out, 0));
+    advance_mirror(c, reps * c->graph_steps);
+    return AH_OK;
+}
+
 void release(ah_ctx *c) {
     if (!c)
         return;
-    void *ptrs[] = { c->d_desc, c->d_step, c->d_coef, c->d_slots, c->d_obs, c->d_gauss };
+    if (c->gexec)
+        (void)hipGraphExecDestroy(c->gexec);
+    if (c->ev_in)
+        (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out)
+        (void)hipEventDestroy(c->ev_out);
+    if (c->gstream)
+        (void)hipStreamDestroy(c->gstream);
+    void *ptrs[] = { c->d_desc, c->d_step, c->d_coef, c->d_slots, c->d_obs, c->d_gauss, c->d_items };
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -227,7 +401,6 @@ void release(ah_ctx *c) {
 }
 
 } // namespace
-
 
 extern "C" {
 
@@ -267,6 +440,7 @@ int ah_init(ah_ctx **out, int32_t n_real, const ah_params *p, const ah_buffers *
     c->stream = (hipStream_t)hip_stream;
     c->p.assign(p, p + n_real);
     c->step.resize(n_real);
+    c->cz.assign(n_real, 0);
 
     std::vector<RealDesc> desc(n_real);
     for (int r = 0; r < n_real; ++r) {
@@ -277,7 +451,7 @@ int ah_init(ah_ctx **out, int32_t n_real, const ah_params *p, const ah_buffers *
         d.ny = q.ny;
         d.nz = q.nz;
         d.elem = c->prec == AH_FP64 ? 8 : 4;
-        d.N = (int64_t)q.nx * q.ny * q.nz;
+        d.N = sites_of(q);
         d.dx = q.dx;
         d.dt = q.dt;
         d.tau0 = q.tau0;
@@ -376,19 +550,25 @@ int ah_step(ah_ctx *c, int64_t nsteps, int32_t measure_every, ah_obs *out, int64
     }
 
     size_t next = 0;
-    for (int64_t i = 0; i < nsteps; ++i) {
-        const bool measuring = next < meas.size() && meas_at[next] == i;
-        TRY(launch_bookkeep(c, 1));
-        for (int r = 0; r < c->nreal; ++r) {
-            const ah_params &q = c->p[r];
-            if (q.n_end > 0 && c->step[r] >= q.n_end)
-                continue;
-            Slot *slot = measuring && meas[next][r] ? c->d_slots + next * c->nreal + r : nullptr;
-            TRY(launch_step(c, r, slot));
-            ++c->step[r];
-        }
-        if (measuring)
+    int64_t i = 0;
+    while (i < nsteps) {
+        if (next < meas.size() && meas_at[next] == i) {
+            TRY(launch_one_step(c, c->d_slots + next * c->nreal, meas[next].data(), true));
+            advance_mirror(c, 1);
             ++next;
+            ++i;
+            continue;
+        }
+        const int64_t stop = next < meas.size() ? meas_at[next] : nsteps;
+        if (c->graph_steps > 0 && stop - i >= c->graph_steps) {
+            const int64_t reps = (stop - i) / c->graph_steps;
+            TRY(run_graph(c, reps));
+            i += reps * c->graph_steps;
+            continue;
+        }
+        TRY(launch_one_step(c, nullptr, nullptr, true));
+        advance_mirror(c, 1);
+        ++i;
     }
 
     if (measure_every > 0) {
@@ -421,9 +601,8 @@ int ah_measure(ah_ctx *c, ah_obs *out, int8_t *wind_dev) {
     TRY(launch_bookkeep(c, 0));
     int64_t off = 0;
     for (int r = 0; r < c->nreal; ++r) {
-        const ah_params &q = c->p[r];
         TRY(launch_measure(c, r, c->d_slots + r, wind_dev ? wind_dev + off : nullptr));
-        off += 3 * (int64_t)q.nx * q.ny * q.nz;
+        off += 3 * sites_of(c->p[r]);
     }
     TRY(launch_finalize(c, c->nreal));
     HIP_TRY(c, hipMemcpyAsync(out, c->d_obs, c->nreal * sizeof(ah_obs), hipMemcpyDeviceToHost,
@@ -445,9 +624,7 @@ int ah_gauss_residual(ah_ctx *c, double *max_abs, double *rms) {
     TRY(launch_zero(c, c->d_gauss, c->nreal * 2 * sizeof(unsigned long long)));
     TRY(launch_bookkeep(c, 0));
     for (int r = 0; r < c->nreal; ++r) {
-        const ah_params &q = c->p[r];
-        const int64_t N = (int64_t)q.nx * q.ny * q.nz;
-        dim3 grid(grid_for(N, kMeasureThreads, 4096));
+        dim3 grid(grid_for(sites_of(c->p[r]), kMeasureThreads, 4096));
         if (c->prec == AH_FP64)
             hipLaunchKernelGGL(k_gauss<double>, grid, dim3(kMeasureThreads), 0, c->stream,
                                c->d_desc, c->d_coef, r, c->d_gauss + 2 * r);
@@ -464,9 +641,8 @@ int ah_gauss_residual(ah_ctx *c, double *max_abs, double *rms) {
         double m, s;
         std::memcpy(&m, &h[2 * r], sizeof m);
         std::memcpy(&s, &h[2 * r + 1], sizeof s);
-        const ah_params &q = c->p[r];
         max_abs[r] = m;
-        rms[r] = std::sqrt(s / ((double)q.nx * q.ny * q.nz));
+        rms[r] = std::sqrt(s / (double)sites_of(c->p[r]));
     }
     return AH_OK;
 }
@@ -499,7 +675,180 @@ int ah_set_kernel(ah_ctx *c, int32_t kernel, int32_t tile_y, int32_t chunk_z) {
         return fail(c, AH_E_INVALID, "tiled kernel needs nx %% 64 == 0");
     c->kernel = kernel;
     c->tile_y = tile_y;
-    c->chunk_z = chunk_z;
+    c->cz.assign(c->nreal, chunk_z);
+    invalidate_plans(c);
+    return AH_OK;
+}
+
+int ah_set_launch(ah_ctx *c, int32_t batched, int32_t graph_steps) {
+    if (!c)
+        return fail(nullptr, AH_E_INVALID, "NULL context");
+    c->err.clear();
+    if ((batched != 0 && batched != 1) || graph_steps < 0 || graph_steps > 4096)
+        return fail(c, AH_E_INVALID, "batched must be 0 or 1 and graph_steps in 0..4096");
+    c->batched = batched;
+    c->graph_steps = graph_steps;
+    invalidate_plans(c);
+    return AH_OK;
+}
+
+int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
+    if (!c)
+        return fail(nullptr, AH_E_INVALID, "NULL context");
+    c->err.clear();
+    if (c->kernel == AH_KERNEL_PLAIN || !tiled_ok(c))
+        return fail(c, AH_E_STATE, "autotuning needs the tiled kernel (nx %% 64 == 0)");
+    const bool fp64 = c->prec == AH_FP64;
+    const int ty_cap = c->batched ? tiled_ty_max(fp64, MODE_STEP_MEASURE) : tiled_ty_max(fp64, MODE_STEP);
+    std::vector<int> tys;
+    for (int t : { 4, 8, 16 })
+        if (tiled_ty_valid(fp64, t) && t <= ty_cap)
+            tys.push_back(t);
+
+    // distinct shapes; each is timed on a scratch lattice of its own, so the
+    // caller's fields are not touched
+    struct Shape {
+        int nx, ny, nz, count;
+        std::vector<double> ms;   // per candidate tile height: est. ms per step
+        std::vector<int> cz;      // per candidate tile height: best z-chunk
+    };
+    std::vector<Shape> shapes;
+    std::vector<int> shape_of(c->nreal);
+    for (int r = 0; r < c->nreal; ++r) {
+        const ah_params &q = c->p[r];
+        int k = 0;
+        while (k < (int)shapes.size() &&
+               !(shapes[k].nx == q.nx && shapes[k].ny == q.ny && shapes[k].nz == q.nz))
+            ++k;
+        if (k == (int)shapes.size())
+            shapes.push_back(Shape{ q.nx, q.ny, q.nz, 0, {}, {} });
+        shapes[k].count++;
+        shape_of[r] = k;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    RealDesc *d_desc = nullptr;
+    Coef *d_coef = nullptr;
+    int64_t *d_step = nullptr;
+    char *scratch = nullptr;
+    int rc = AH_OK;
+    auto hip_ok = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && rc == AH_OK)
+            rc = fail(c, AH_E_HIP, "autotune: %s failed: %s", what, hipGetErrorString(e));
+        return rc == AH_OK;
+    };
+    if (hip_ok(hipEventCreate(&e0), "hipEventCreate") && hip_ok(hipEventCreate(&e1), "hipEventCreate") &&
+        hip_ok(hipMalloc(&d_desc, sizeof(RealDesc)), "hipMalloc") &&
+        hip_ok(hipMalloc(&d_coef, sizeof(Coef)), "hipMalloc") &&
+        hip_ok(hipMalloc(&d_step, sizeof(int64_t)), "hipMalloc")) {
+        for (Shape &sh : shapes) {
+            // time a slab of at most 128 planes: the cost per plane is what is tuned
+            const int nzs = std::min(sh.nz, 128);
+            const int64_t N = (int64_t)sh.nx * sh.ny * nzs;
+            const size_t bytes = (size_t)N * 15 * (fp64 ? 8 : 4);
+            if (!hip_ok(hipMalloc(&scratch, bytes), "hipMalloc(scratch)"))
+                break;
+            const ah_params &q0 = c->p[0];
+            RealDesc d{};
+            d.base = scratch;
+            d.nx = sh.nx;
+            d.ny = sh.ny;
+            d.nz = nzs;
+            d.elem = fp64 ? 8 : 4;
+            d.N = N;
+            d.dx = q0.dx;
+            d.dt = q0.dt;
+            d.tau0 = 1.0;
+            d.tau_ref = 2.0;
+            d.era_p = 1.0;
+            d.s = 1.0;
+            d.lambda0 = q0.lambda0;
+            d.e0 = q0.e0;
+            d.sigma = q0.sigma;
+            const int64_t s0 = 0;
+            hip_ok(hipMemcpyAsync(d_desc, &d, sizeof d, hipMemcpyHostToDevice, c->stream), "copy");
+            hip_ok(hipMemcpyAsync(d_step, &s0, sizeof s0, hipMemcpyHostToDevice, c->stream), "copy");
+            dim3 ig(grid_for(N, 256, 8192));
+            if (fp64)
+                hipLaunchKernelGGL(k_init<double>, ig, dim3(256), 0, c->stream, d_desc, 0,
+                                   (int)AH_INIT_RANDOM_PHASE, (uint64_t)12345);
+            else
+                hipLaunchKernelGGL(k_init<float>, ig, dim3(256), 0, c->stream, d_desc, 0,
+                                   (int)AH_INIT_RANDOM_PHASE, (uint64_t)12345);
+            hipLaunchKernelGGL(k_bookkeep, dim3(1), dim3(64), 0, c->stream, d_desc, d_step, d_coef,
+                               1, 0);
+            hip_ok(hipGetLastError(), "launch");
+            for (int t : tys) {
+                double best = 1e300;
+                int best_cz = 8;
+                for (int z : { 8, 16, 32, 64, 128 }) {
+                    if (z > nzs || rc != AH_OK)
+                        continue;
+                    for (int k = 0; k < 4 && rc == AH_OK; ++k) {
+                        if (k == 1)
+                            hip_ok(hipEventRecord(e0, c->stream), "hipEventRecord");
+                        hip_ok((hipError_t)launch_step_tiled(fp64, MODE_STEP, d_desc, d_coef, 0,
+                                                             sh.nx, sh.ny, nzs, t, z, nullptr,
+                                                             nullptr, c->stream),
+                               "tiled launch");
+                    }
+                    float ms = 0.f;
+                    hip_ok(hipEventRecord(e1, c->stream), "hipEventRecord");
+                    hip_ok(hipEventSynchronize(e1), "hipEventSynchronize");
+                    hip_ok(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                    const double per_plane = ms / 3.0 / nzs;
+                    if (per_plane < best) {
+                        best = per_plane;
+                        best_cz = z;
+                    }
+                }
+                sh.ms.push_back(best * sh.nz);
+                sh.cz.push_back(best_cz);
+            }
+            (void)hipStreamSynchronize(c->stream);
+            (void)hipFree(scratch);
+            scratch = nullptr;
+            if (rc != AH_OK)
+                break;
+        }
+    }
+    (void)hipStreamSynchronize(c->stream);
+    if (scratch)
+        (void)hipFree(scratch);
+    if (d_desc)
+        (void)hipFree(d_desc);
+    if (d_coef)
+        (void)hipFree(d_coef);
+    if (d_step)
+        (void)hipFree(d_step);
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    if (rc != AH_OK)
+        return rc;
+
+    // one tile height for the context: least total estimated time per step
+    int bi = 0;
+    double bt = 1e300;
+    for (size_t i = 0; i < tys.size(); ++i) {
+        double tot = 0.0;
+        for (const Shape &sh : shapes)
+            tot += sh.ms[i] * sh.count;
+        if (tot < bt) {
+            bt = tot;
+            bi = (int)i;
+        }
+    }
+    c->tile_y = tys[bi];
+    for (int r = 0; r < c->nreal; ++r)
+        c->cz[r] = shapes[shape_of[r]].cz[bi];
+    invalidate_plans(c);
+    if (tile_y)
+        *tile_y = c->tile_y;
+    if (chunk_z)
+        for (int r = 0; r < c->nreal; ++r)
+            chunk_z[r] = c->cz[r];
     return AH_OK;
 }
 
@@ -507,6 +856,8 @@ int ah_free(ah_ctx *c) {
     if (!c)
         return AH_OK;
     hipError_t e = hipStreamSynchronize(c->stream);
+    if (c->gstream && e == hipSuccess)
+        e = hipStreamSynchronize(c->gstream);
     release(c);
     return e == hipSuccess ? AH_OK : AH_E_HIP;
 }

@@ -61,22 +61,26 @@ template <int TY> struct TileGeom {
     }
 };
 
-// sin Xi_ij(s) = Im[U_i(s) U_j(s+i) conj(U_i(s+j)) conj(U_j(s))], phasors as (cos, sin)
+// sin Xi_ij(s) = Im[U_i(s) U_j(s+i) conj(U_i(s+j)) conj(U_j(s))], phasors as
+// (cos, sin).  Written with explicit fused multiply-adds so that its rounding
+// does not depend on where the compiler inlines it: the same plaquette is
+// formed in the chunk prologue and in the main loop, and results must not
+// depend on the z-chunk.
 template <typename T>
 __device__ __forceinline__ T plaq_sin(T aic, T ais, T bjc, T bjs, T cic, T cis, T djc, T djs) {
-    const T wr = aic * djc + ais * djs, wi = ais * djc - aic * djs;   // U_i(s) conj(U_j(s))
-    const T vr = bjc * cic + bjs * cis, vi = bjs * cic - bjc * cis;   // U_j(s+i) conj(U_i(s+j))
-    return wr * vi + wi * vr;
+    const T wr = fma(aic, djc, ais * djs), wi = fma(ais, djc, -(aic * djs));  // U_i(s) conj(U_j(s))
+    const T vr = fma(bjc, cic, bjs * cis), vi = fma(bjs, cic, -(bjc * cis));  // U_j(s+i) conj(U_i(s+j))
+    return fma(wr, vi, wi * vr);
 }
 
 // 1 - cos Xi_ij(s) = |conj(w) - v|^2 / 2 with w, v as in plaq_sin (|w v| = 1);
 // this form keeps its relative accuracy for small Xi.
 template <typename T>
 __device__ __forceinline__ T plaq_omc(T aic, T ais, T bjc, T bjs, T cic, T cis, T djc, T djs) {
-    const T wr = aic * djc + ais * djs, wi = ais * djc - aic * djs;
-    const T vr = bjc * cic + bjs * cis, vi = bjs * cic - bjc * cis;
+    const T wr = fma(aic, djc, ais * djs), wi = fma(ais, djc, -(aic * djs));
+    const T vr = fma(bjc, cic, bjs * cis), vi = fma(bjs, cic, -(bjc * cis));
     const T a = wr - vr, b = wi + vi;
-    return (T)0.5 * (a * a + b * b);
+    return (T)0.5 * fma(a, a, b * b);
 }
 
 // wrap count of a link: [u]_pi = u - 2 pi m (Eq. (11)), computed in FP64
@@ -94,9 +98,21 @@ __device__ __forceinline__ int wrap_mod(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block b on XCD
+// b % 8).  This bijection of [0, nb) gives XCD i the contiguous run
+// [start_i, start_i + count_i) of tile numbers, so tiles that share halo rows
+// run on one XCD and meet in its L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int xcd = b & 7, per = nb >> 3, rem = nb & 7;
+    return xcd * per + min(xcd, rem) + (b >> 3);
+}
+
+// One tile (64 x TY sites, planes [z0, z0 + cz)) of one realization, tiles
+// numbered x-fastest, then y, then z-chunk.  Every thread of the block calls
+// it with the same arguments.
 template <typename T, int TY, int MODE>
-__global__ void __launch_bounds__(64 * TY)
-k_step_tiled(const RealDesc *descs, const Coef *coefs, int r, int cz, Slot *slot, int8_t *wind) {
+__device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int tile, int cz,
+                                           Slot *slot, int8_t *wind) {
     constexpr bool MEAS = MODE != MODE_STEP;
     constexpr bool UPD = MODE != MODE_MEASURE;
     using G = TileGeom<TY>;
@@ -105,18 +121,8 @@ k_step_tiled(const RealDesc *descs, const Coef *coefs, int r, int cz, Slot *slot
     __shared__ double lth[2][SM];      // arg phi (measuring modes)
     __shared__ T lar[2][3][SM];        // raw link angles (measuring modes)
 
-    const RealDesc d = descs[r];
-    const Coef c = coefs[r];
-    if (UPD && !c.active)
-        return;
     const int nx = d.nx, ny = d.ny, nz = d.nz;
     const int ntx = nx >> 6, nty = (ny + TY - 1) / TY;
-
-    // XCD-aware tile order: block b runs on XCD b % 8; XCD i gets tiles
-    // [start_i, start_i + count_i) in x-fastest, then y, then z-chunk order.
-    const int nb = gridDim.x, b = blockIdx.x;
-    const int xcd = b & 7, per = nb >> 3, rem = nb & 7;
-    const int tile = xcd * per + min(xcd, rem) + (b >> 3);
     const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
     const int x0 = tx << 6, y0 = ty * TY, z0 = tz * cz;
     const int z1 = min(z0 + cz, nz);
@@ -386,11 +392,54 @@ k_step_tiled(const RealDesc *descs, const Coef *coefs, int r, int cz, Slot *slot
     }
 
     if (MEAS) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (tile == 0 && threadIdx.x == 0) {
             slot->c = c;
             slot->measured = 1;
         }
         block_accumulate<A_COUNT, C_COUNT, TY>(msum, mcnt, slot->acc.s, slot->acc.c);
+        __syncthreads();   // the reduction's LDS is reused by the next tile of a batch
+    }
+}
+
+// One realization: one block per tile.
+template <typename T, int TY, int MODE>
+__global__ void __launch_bounds__(64 * TY)
+k_step_tiled(const RealDesc *descs, const Coef *coefs, int r, int cz, Slot *slot, int8_t *wind) {
+    const RealDesc d = descs[r];
+    const Coef c = coefs[r];
+    if (MODE != MODE_MEASURE && !c.active)
+        return;
+    tiled_tile<T, TY, MODE>(d, c, xcd_remap(blockIdx.x, gridDim.x), cz, slot, wind);
+}
+
+// A work item of the batched kernel: tile `tile` of realization r, with that
+// realization's z-chunk cz.
+struct BatchItem {
+    int32_t r, tile, cz, pad;
+};
+
+// Many realizations in one launch: a persistent grid walks the item list in
+// rounds of gridDim.x items; within a round the XCD remap keeps consecutive
+// items (neighbouring tiles of one realization) on one XCD.  Realizations
+// that reached their n_end are skipped.  In the measuring mode every active
+// realization r measures into slots[r].
+template <typename T, int TY, int MODE>
+__global__ void __launch_bounds__(64 * TY)
+k_step_batch(const RealDesc *descs, const Coef *coefs, const BatchItem *items, int n_items,
+             Slot *slots) {
+    const int g = gridDim.x;
+    const int b = xcd_remap(blockIdx.x, g);
+    for (int base = 0; base < n_items; base += g) {
+        const int it = base + b;
+        if (it >= n_items)
+            break;
+        const BatchItem item = items[it];
+        const Coef c = coefs[item.r];
+        if (!c.active)
+            continue;
+        const RealDesc d = descs[item.r];
+        tiled_tile<T, TY, MODE>(d, c, item.tile, item.cz,
+                                MODE == MODE_STEP ? nullptr : slots + item.r, nullptr);
     }
 }
 
@@ -465,6 +514,67 @@ inline int launch_step_tiled(bool fp64, int mode, const RealDesc *desc, const Co
           : mode == MODE_STEP_MEASURE ? launch_tiled_mode<float, MODE_STEP_MEASURE>(ty, desc, coef, r, nx, ny, nz, cz, slot, wind, stream)
           : launch_tiled_mode<float, MODE_MEASURE>(ty, desc, coef, r, nx, ny, nz, cz, slot, wind, stream);
     }
+    return (int)e;
+}
+
+// Largest tile height of a mode (the measuring modes hold ~220 VGPRs).
+inline int tiled_ty_max(bool fp64, int mode) {
+    return mode != MODE_STEP ? (fp64 ? 4 : 8) : (fp64 ? 8 : 16);
+}
+
+template <typename T, int TY, int MODE>
+hipError_t batch_grid_ty(int *grid) {
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_batch<T, TY, MODE>, 64 * TY, 0);
+    *grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    return e;
+}
+
+template <typename T, int TY, int MODE>
+hipError_t launch_batch_ty(const RealDesc *desc, const Coef *coef, const BatchItem *items,
+                           int n_items, Slot *slots, int grid, hipStream_t stream) {
+    if (grid > n_items)
+        grid = n_items;
+    if (grid < 1)
+        return hipSuccess;
+    hipLaunchKernelGGL((k_step_batch<T, TY, MODE>), dim3((unsigned)grid), dim3(64 * TY), 0, stream,
+                       desc, coef, items, n_items, slots);
+    return hipGetLastError();
+}
+
+// Dispatch over (precision, tile height, mode) of the batched kernel.  With
+// grid_out != NULL only the resident-block count of that kernel is returned
+// (occupancy x compute units); otherwise the kernel is launched on `grid`
+// blocks.  Tile heights: FP32 2, 4, 8 (16 for MODE_STEP); FP64 2, 4 (8 for
+// MODE_STEP).
+inline int batch_dispatch(bool fp64, int mode, int ty, const RealDesc *desc, const Coef *coef,
+                          const BatchItem *items, int n_items, Slot *slots, int grid,
+                          hipStream_t stream, int *grid_out) {
+    if (ty > tiled_ty_max(fp64, mode) || !tiled_ty_valid(fp64, ty))
+        return (int)hipErrorInvalidValue;
+#define AH_BATCH(T, TY_, M)                                                                        \
+    (grid_out ? batch_grid_ty<T, TY_, M>(grid_out)                                                 \
+              : launch_batch_ty<T, TY_, M>(desc, coef, items, n_items, slots, grid, stream))
+    hipError_t e = hipErrorInvalidValue;
+    if (fp64) {
+        if (mode == MODE_STEP)
+            e = ty == 2 ? AH_BATCH(double, 2, MODE_STEP) : ty == 4 ? AH_BATCH(double, 4, MODE_STEP)
+                                                                   : AH_BATCH(double, 8, MODE_STEP);
+        else
+            e = ty == 2 ? AH_BATCH(double, 2, MODE_STEP_MEASURE) : AH_BATCH(double, 4, MODE_STEP_MEASURE);
+    } else {
+        if (mode == MODE_STEP)
+            e = ty == 2 ? AH_BATCH(float, 2, MODE_STEP) : ty == 4 ? AH_BATCH(float, 4, MODE_STEP)
+              : ty == 8 ? AH_BATCH(float, 8, MODE_STEP) : AH_BATCH(float, 16, MODE_STEP);
+        else
+            e = ty == 2 ? AH_BATCH(float, 2, MODE_STEP_MEASURE)
+              : ty == 4 ? AH_BATCH(float, 4, MODE_STEP_MEASURE) : AH_BATCH(float, 8, MODE_STEP_MEASURE);
+    }
+#undef AH_BATCH
     return (int)e;
 }
 

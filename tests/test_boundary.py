@@ -22,7 +22,7 @@ def declared_functions():
 def test_library_exports_every_declared_entry_point():
     lib = AH.load_library()
     names = declared_functions()
-    assert len(names) == 10
+    assert len(names) == 12
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(B.EXPORTED) == names

@@ -312,3 +312,87 @@ def test_fused_measurement_on_identical_input(O, prec):
         assert getattr(g, k) == pytest.approx(getattr(o, k), rel=rel), k
     for k in ("num", "den", "v2"):
         assert np.allclose(getattr(g, k), getattr(o, k), rtol=rel * 10, atol=1e-20), k
+
+
+def _ensemble(prec=AH.AH_FP32):
+    """Uneven realizations, mixed eras and s, one stopping early (n_end)."""
+    return [AH.Params(64, 8, 8, precision=prec, tau_ref=2.0, era_p=1.0, s=1.0, seed=31),
+            AH.Params(128, 16, 12, precision=prec, tau_ref=3.0, era_p=2.0, s=0.0, seed=32),
+            AH.Params(64, 24, 20, precision=prec, tau_ref=2.5, era_p=1.0, s=0.0, seed=33, n_end=9),
+            AH.Params(192, 6, 5, precision=prec, tau_ref=1.5, era_p=2.0, s=0.0, seed=34)]
+
+
+def _run_ensemble(ps, batched, graph_steps, nsteps=17, measure_every=5):
+    with AH.Context(ps, [AH.alloc_planes(p) for p in ps]) as c:
+        c.set_launch(batched, graph_steps)
+        obs = c.step(nsteps, measure_every=measure_every)
+        fields = [c.fields(r).clone() for r in range(len(ps))]
+        steps = [c.current_step(r) for r in range(len(ps))]
+    return fields, obs, steps
+
+
+@pytest.mark.parametrize("prec", [AH.AH_FP32, AH.AH_FP64])
+def test_batched_and_graph_launches_equal_per_realization(prec):
+    """One persistent launch per step (and graph replay) gives bit-identical
+    fields and the same observations as one launch per realization."""
+    _print_case(test="batched", prec=prec)
+    ps = _ensemble(prec)
+    ref_f, ref_o, ref_s = _run_ensemble(ps, False, 0)
+    assert ref_s == [17, 17, 9, 17]
+    for batched, g in ((True, 0), (True, 3), (False, 4)):
+        f, o, s = _run_ensemble(ps, batched, g)
+        assert s == ref_s
+        for r in range(len(ps)):
+            assert torch.equal(f[r], ref_f[r]), (batched, g, r)
+        assert len(o) == len(ref_o)
+        for row, ref_row in zip(o, ref_o):
+            for a, b in zip(row, ref_row):
+                assert a.step == b.step and a.n_wind_dir == b.n_wind_dir
+                if a.step >= 0:
+                    assert a.energy == pytest.approx(b.energy, rel=1e-12)
+                    assert a.sum_lag == pytest.approx(b.sum_lag, rel=1e-12)
+    # the early-stopping realization reports no measurement after its n_end
+    assert [row[2].step for row in ref_o] == [0, 5, -1, -1]
+
+
+def test_graph_replay_repeats_with_eager_work_between():
+    """The captured graph is replayed over several calls, with the program's
+    own eager work and synchronisation between them; every replay matches the
+    eager run."""
+    _print_case(test="graph_replay")
+    ps = _ensemble(AH.AH_FP32)[:2]
+    eager = AH.Context(ps, [AH.alloc_planes(p) for p in ps])
+    graph = AH.Context(ps, [AH.alloc_planes(p) for p in ps])
+    graph.set_launch(True, 4)
+    try:
+        for k in range(4):
+            eager.step(9)
+            graph.step(9)
+            scratch = torch.randn(1 << 20, device="cuda")
+            _ = float(scratch.sum())                    # eager library work between replays
+            graph.measure()
+            torch.cuda.synchronize()
+            for r in range(2):
+                assert torch.equal(graph.fields(r), eager.fields(r)), (k, r)
+    finally:
+        eager.close()
+        graph.close()
+
+
+def test_autotune_keeps_fields_and_results():
+    _print_case(test="autotune")
+    ps = _ensemble(AH.AH_FP32)
+    with AH.Context(ps, [AH.alloc_planes(p) for p in ps]) as c:
+        c.step(3)
+        before = [c.fields(r).clone() for r in range(len(ps))]
+        ty, cz = c.autotune()
+        assert ty in (4, 8, 16) and len(cz) == len(ps) and all(z >= 1 for z in cz)
+        for r in range(len(ps)):
+            assert torch.equal(c.fields(r), before[r])
+        c.set_launch(True, 2)
+        c.step(6)
+        tuned = [c.fields(r).clone() for r in range(len(ps))]
+    with AH.Context(ps, [AH.alloc_planes(p) for p in ps]) as c:
+        c.step(9)
+        for r in range(len(ps)):
+            assert torch.equal(c.fields(r), tuned[r]), r
