@@ -132,9 +132,9 @@ def run_ensemble(AH, torch, batched, graph_steps, tune):
 
 
 def cpu_baseline():
-    """The FP64 oracle (test infrastructure) on a bounded sample: 256^3, 6 steps."""
+    """The FP64 oracle (test infrastructure) on a bounded sample: 256^3, 24 steps."""
     import oracle as O
-    n, k = 256, 6
+    n, k = 256, 24
     p = O.Params(n, n, n, tau0=1.0, tau_ref=n * 0.5 / 2, era_p=2.0, s=0.0, seed=2024)
     st = O.init_random_phase(p)
     st = O.step(p, 10, st)                     # warm the pages

@@ -94,6 +94,7 @@ def _load():
         lib.or_measure.argtypes = [P(_Params), C.c_int64, D, P(_Obs), C.c_void_p]
         lib.or_gauss.argtypes = [P(_Params), C.c_int64, D, D, D, C.c_void_p]
         lib.or_threads.restype = C.c_int
+        lib.or_step_sites.argtypes = [P(_Params), C.c_int64, D, C.c_int64, C.c_void_p, D]
         _lib = lib
     return _lib
 
@@ -146,6 +147,15 @@ def step(p: Params, n: int, st) -> np.ndarray:
     st = _state(p, st)
     out = np.empty_like(st)
     _load().or_step(C.byref(p._c()), n, _dptr(st), _dptr(out))
+    return out
+
+
+def step_sites(p: Params, n: int, st, idx) -> np.ndarray:
+    """S_{n+1} at the given flat site indices only: array (len(idx), 10)."""
+    st = _state(p, st)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty((idx.size, 10), dtype=np.float64)
+    _load().or_step_sites(C.byref(p._c()), n, _dptr(st), idx.size, idx.ctypes.data, _dptr(out))
     return out
 
 

@@ -144,6 +144,76 @@ static double plaquette(const or_params *p, const double *st, int x, int y, int 
 }
 
 /*
+ * The update of one site, Sec. 2, Eqs. (4)-(7): S_{n+1} at site (x,y,z) from
+ * S_n = (phi^n, A^n, Pi^{n-1/2}, E^{n-1/2}).  The ten new values (plane order)
+ * go to out10.
+ */
+static void update_site(const or_params *p, const or_coeffs *c, const double *in, int x, int y,
+                        int z, double out10[10])
+{
+    size_t N = sites(p);
+    size_t o = nb(p, x, y, z, 0, 0, 0);
+    double pr = in[PHR * N + o], pim = in[PHI * N + o];
+
+    /* Eq. (4): covariant Laplacian
+     * sum_j [ e^{iA_j^x} phi^{x+j} - 2 phi^x + e^{-iA_j^{x-j}} phi^{x-j} ] */
+    double lr = 0.0, li = 0.0;
+    for (int j = 0; j < 3; ++j) {
+        const int *u = UNIT[j];
+        size_t fp = nb(p, x, y, z, u[0], u[1], u[2]);
+        size_t fm = nb(p, x, y, z, -u[0], -u[1], -u[2]);
+        double ajp = in[(AX + j) * N + o];
+        double ajm = in[(AX + j) * N + fm];
+        double qr = in[PHR * N + fp], qi = in[PHI * N + fp];
+        double mr = in[PHR * N + fm], mi = in[PHI * N + fm];
+        /* e^{i a} (qr + i qi) */
+        lr += cos(ajp) * qr - sin(ajp) * qi;
+        li += cos(ajp) * qi + sin(ajp) * qr;
+        /* e^{-i a} (mr + i mi) */
+        lr += cos(ajm) * mr + sin(ajm) * mi;
+        li += cos(ajm) * mi - sin(ajm) * mr;
+        lr -= 2.0 * pr;
+        li -= 2.0 * pim;
+    }
+    double v = pr * pr + pim * pim - p->sigma * p->sigma;
+    double pinr = c->c1 * in[PIR * N + o] + c->c2 * lr - c->c3 * v * pr;
+    double pini = c->c1 * in[PII * N + o] + c->c2 * li - c->c3 * v * pim;
+    out10[PIR] = pinr;
+    out10[PII] = pini;
+
+    /* Eq. (6) */
+    out10[PHR] = pr + p->dt * pinr;
+    out10[PHI] = pim + p->dt * pini;
+
+    /* Eq. (5), for each link direction i */
+    for (int i = 0; i < 3; ++i) {
+        const int *u = UNIT[i];
+        size_t fp = nb(p, x, y, z, u[0], u[1], u[2]);
+        double ai = in[(AX + i) * N + o];
+        /* Im[ conj(phi^{x+i}) e^{-i A_i^x} phi^x ] */
+        double qr = in[PHR * N + fp], qi = in[PHI * N + fp];
+        double wr = cos(ai) * pr + sin(ai) * pim;  /* e^{-ia} phi^x */
+        double wi = cos(ai) * pim - sin(ai) * pr;
+        double cur = qr * wi - qi * wr;
+        /* sum_{j != i} [ sin Xi_ij^x - sin Xi_ij^{x-j} ] */
+        double curl = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            if (j == i)
+                continue;
+            const int *w = UNIT[j];
+            curl += sin(plaquette(p, in, x, y, z, i, j));
+            curl -= sin(plaquette(p, in, (x - w[0] + p->nx) % p->nx,
+                                  (y - w[1] + p->ny) % p->ny,
+                                  (z - w[2] + p->nz) % p->nz, i, j));
+        }
+        double en = c->d1 * in[(EX + i) * N + o] + c->d3 * cur - c->d2 * curl;
+        out10[EX + i] = en;
+        /* Eq. (7) */
+        out10[AX + i] = ai + p->dt * en;
+    }
+}
+
+/*
  * One staggered leapfrog step, Sec. 2, Eqs. (4)-(7): from
  * S_n = (phi^n, A^n, Pi^{n-1/2}, E^{n-1/2}) to S_{n+1}.  All right-hand sides
  * read S_n only.
@@ -155,70 +225,29 @@ void or_step(const or_params *p, int64_t n, const double *in, double *out)
     or_coefficients(p, n, &c);
 
 #pragma omp parallel for schedule(static)
-    for (int z = 0; z < p->nz; ++z) {
-        for (int y = 0; y < p->ny; ++y) {
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
+                double v[10];
+                update_site(p, &c, in, x, y, z, v);
                 size_t o = nb(p, x, y, z, 0, 0, 0);
-                double pr = in[PHR * N + o], pim = in[PHI * N + o];
-
-                /* Eq. (4): covariant Laplacian
-                 * sum_j [ e^{iA_j^x} phi^{x+j} - 2 phi^x + e^{-iA_j^{x-j}} phi^{x-j} ] */
-                double lr = 0.0, li = 0.0;
-                for (int j = 0; j < 3; ++j) {
-                    const int *u = UNIT[j];
-                    size_t fp = nb(p, x, y, z, u[0], u[1], u[2]);
-                    size_t fm = nb(p, x, y, z, -u[0], -u[1], -u[2]);
-                    double ajp = in[(AX + j) * N + o];
-                    double ajm = in[(AX + j) * N + fm];
-                    double qr = in[PHR * N + fp], qi = in[PHI * N + fp];
-                    double mr = in[PHR * N + fm], mi = in[PHI * N + fm];
-                    /* e^{i a} (qr + i qi) */
-                    lr += cos(ajp) * qr - sin(ajp) * qi;
-                    li += cos(ajp) * qi + sin(ajp) * qr;
-                    /* e^{-i a} (mr + i mi) */
-                    lr += cos(ajm) * mr + sin(ajm) * mi;
-                    li += cos(ajm) * mi - sin(ajm) * mr;
-                    lr -= 2.0 * pr;
-                    li -= 2.0 * pim;
-                }
-                double v = pr * pr + pim * pim - p->sigma * p->sigma;
-                double pinr = c.c1 * in[PIR * N + o] + c.c2 * lr - c.c3 * v * pr;
-                double pini = c.c1 * in[PII * N + o] + c.c2 * li - c.c3 * v * pim;
-                out[PIR * N + o] = pinr;
-                out[PII * N + o] = pini;
-
-                /* Eq. (6) */
-                out[PHR * N + o] = pr + p->dt * pinr;
-                out[PHI * N + o] = pim + p->dt * pini;
-
-                /* Eq. (5), for each link direction i */
-                for (int i = 0; i < 3; ++i) {
-                    const int *u = UNIT[i];
-                    size_t fp = nb(p, x, y, z, u[0], u[1], u[2]);
-                    double ai = in[(AX + i) * N + o];
-                    /* Im[ conj(phi^{x+i}) e^{-i A_i^x} phi^x ] */
-                    double qr = in[PHR * N + fp], qi = in[PHI * N + fp];
-                    double wr = cos(ai) * pr + sin(ai) * pim;  /* e^{-ia} phi^x */
-                    double wi = cos(ai) * pim - sin(ai) * pr;
-                    double cur = qr * wi - qi * wr;
-                    /* sum_{j != i} [ sin Xi_ij^x - sin Xi_ij^{x-j} ] */
-                    double curl = 0.0;
-                    for (int j = 0; j < 3; ++j) {
-                        if (j == i)
-                            continue;
-                        const int *w = UNIT[j];
-                        curl += sin(plaquette(p, in, x, y, z, i, j));
-                        curl -= sin(plaquette(p, in, (x - w[0] + p->nx) % p->nx,
-                                              (y - w[1] + p->ny) % p->ny,
-                                              (z - w[2] + p->nz) % p->nz, i, j));
-                    }
-                    double en = c.d1 * in[(EX + i) * N + o] + c.d3 * cur - c.d2 * curl;
-                    out[(EX + i) * N + o] = en;
-                    /* Eq. (7) */
-                    out[(AX + i) * N + o] = ai + p->dt * en;
-                }
+                for (int f = 0; f < 10; ++f)
+                    out[f * N + o] = v[f];
             }
-        }
+}
+
+/* S_{n+1} at the listed sites only: out[k*10 + f] is field f at site idx[k]. */
+void or_step_sites(const or_params *p, int64_t n, const double *in, int64_t nsites,
+                   const int64_t *idx, double *out)
+{
+    or_coeffs c;
+    or_coefficients(p, n, &c);
+    for (int64_t k = 0; k < nsites; ++k) {
+        int64_t s = idx[k];
+        int x = (int)(s % p->nx);
+        int y = (int)((s / p->nx) % p->ny);
+        int z = (int)(s / ((int64_t)p->nx * p->ny));
+        update_site(p, &c, in, x, y, z, out + k * 10);
     }
 }
 

@@ -65,6 +65,10 @@ void or_init_random_phase(const or_params *p, double *state);
 /* S_n -> S_{n+1}; `in` and `out` must not overlap. */
 void or_step(const or_params *p, int64_t n, const double *in, double *out);
 
+/* S_{n+1} at the listed sites only: out[k*10 + f] = field f at site idx[k]. */
+void or_step_sites(const or_params *p, int64_t n, const double *in, int64_t nsites,
+                   const int64_t *idx, double *out);
+
 /* Diagnostics of S_n.  wmap (optional) receives W for the xy, yz, zx
  * plaquettes at each site, as 3 planes of int8. */
 void or_measure(const or_params *p, int64_t n, const double *state,

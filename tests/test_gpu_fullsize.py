@@ -1,0 +1,116 @@
+"""Full-size GPU checks, in the launch configuration bench.py times.
+
+- 512^3 (the benchmark workload): one step of the library against the oracle
+  evaluated site by site on sampled sites (tile edges in x and y, z-chunk
+  edges, lattice boundaries, random interior sites), FP32 and FP64.
+- 256^3 radiation era, s = 1, to tau = 64 (640 steps, diagnostics every 10):
+  fields after 10 steps against the oracle (FP64: 1e-12; FP32 from the
+  FP32-rounded start: 1e-5 per field group), diagnostics at step 10 against
+  the oracle, and string length, xi and <v^2> at the end for FP32 against
+  FP64 (1e-3), with Gauss's law and the zero net winding held throughout.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+AH = pytest.importorskip("paper_1809_00995_amd")
+from tests.gpu_util import (fields_np, group_errors, oracle_params)  # noqa: E402
+
+
+def _edge_coords(n, period):
+    """Coordinates next to every tile / chunk edge of the given period, plus the lattice ends."""
+    c = {0, 1, n - 2, n - 1}
+    for e in range(period, n, period):
+        c.update({e - 1, e})
+    return sorted(x for x in c if 0 <= x < n)
+
+
+def _sample_sites(n, rng, k_random=4000):
+    xs = _edge_coords(n, 64)                 # tile edges in x
+    ys = _edge_coords(n, 4)[:32]             # tile edges in y (heights 4 and 8)
+    zs = _edge_coords(n, 64)                 # z-chunk edges of the default chunking
+    pts = [(x, y, z) for x in xs[::2] for y in ys[::2] for z in zs[::2]]
+    pts += [tuple(v) for v in rng.integers(0, n, size=(k_random, 3))]
+    return np.unique(np.array([x + n * (y + n * z) for x, y, z in pts], dtype=np.int64))
+
+
+@pytest.mark.parametrize("prec", [AH.AH_FP32, AH.AH_FP64])
+def test_512cubed_one_step_on_sampled_sites(O, prec):
+    n = 512
+    print(f"CASE test=512_sampled prec={prec}", flush=True)
+    p = AH.Params(n, n, n, precision=prec, dx=0.5, dt=0.1, tau0=0.0, tau_ref=n * 0.5 / 2,
+                  era_p=2.0, s=0.0, seed=2024)
+    planes = AH.alloc_planes(p)
+    with AH.Context([p], [planes]) as c:
+        c.step(30)
+        torch.cuda.synchronize()
+        idx = _sample_sites(n, np.random.default_rng(7))
+        state = c.fields().double().cpu().numpy()          # S_30, widened to FP64
+        c.step(1)
+        got = c.fields().reshape(10, -1)[:, torch.from_numpy(idx).cuda()].double().cpu().numpy().T
+    ref = O.step_sites(oracle_params(O, p), 30, state, idx)
+    del state
+    tol = 1e-12 if prec == AH.AH_FP64 else 1e-5
+    for g, cols in (("phi", [0, 1]), ("pi", [2, 3]), ("a", [4, 5, 6]), ("e", [7, 8, 9])):
+        scale = np.abs(ref[:, cols]).max()
+        err = np.abs(got[:, cols] - ref[:, cols]).max() / scale
+        print(f"  {g}: max rel err {err:.2e} over {idx.size} sites", flush=True)
+        assert err < tol, g
+
+
+def test_config_256cubed_radiation_run(O):
+    n, steps, every = 256, 640, 10
+    print("CASE test=config_256", flush=True)
+    base = dict(dx=0.5, dt=0.1, tau0=0.0, tau_ref=n * 0.5 / 2, era_p=1.0, s=1.0, seed=1)
+    res = {}
+    for prec in (AH.AH_FP64, AH.AH_FP32):
+        p = AH.Params(n, n, n, precision=prec, **base)
+        with AH.Context([p], [AH.alloc_planes(p)]) as c:
+            c.step(10)
+            f10 = fields_np(c)
+            obs = c.step(steps - 10, measure_every=every)
+            (last,) = c.measure()                   # S_640, tau = 64
+            mx, _ = c.gauss_residual()
+        res[prec] = (p, f10, [o[0] for o in obs] + [last], mx[0])
+    op = oracle_params(O, res[AH.AH_FP64][0])
+    init = O.init_random_phase(op)
+    ref10, oobs = O.run(op, init, 0, 10, measure_every=10)
+    e64 = group_errors(res[AH.AH_FP64][1], ref10)
+    init32 = init.astype(np.float32).astype(np.float64)
+    ref10_32, _ = O.run(op, init32, 0, 10)
+    e32 = group_errors(res[AH.AH_FP32][1], ref10_32)
+    print("  step-10 field errors FP64:", e64, " FP32:", e32, flush=True)
+    assert max(e64.values()) < 1e-12
+    assert max(e32.values()) < 1e-5
+
+    o64, o32 = res[AH.AH_FP64][2], res[AH.AH_FP32][2]
+    assert [o.step for o in o64] == list(range(10, steps, every)) + [steps]
+    # diagnostics of S_10 (first measurement of the call) against the oracle
+    ref_m = O.measure(op, 10, ref10)
+    g = o64[0]
+    assert g.n_wind == ref_m.n_wind
+    for k in ("energy", "sum_lag"):
+        assert getattr(g, k) == pytest.approx(getattr(ref_m, k), rel=1e-9), k
+    assert np.allclose(g.v2, ref_m.v2, rtol=1e-9)
+    # properties held at every measurement
+    for o in o64 + o32:
+        assert o.net_wind_dir == [0, 0, 0] and o.nonfinite == 0
+    assert res[AH.AH_FP64][3] < 1e-12
+    # end time: FP32 against FP64
+    a, b = o32[-1], o64[-1]
+    print(f"  end step {b.step}: n_wind fp64 {b.n_wind} fp32 {a.n_wind}; "
+          f"v2_L {b.v2[0]:.6f} {a.v2[0]:.6f}; v2_V {b.v2[1]:.6f} {a.v2[1]:.6f}; "
+          f"xi_L {b.xi_l:.5f} {a.xi_l:.5f}", flush=True)
+    curve = [(x.step, abs(x.length - y.length) / y.length, abs(x.v2[0] - y.v2[0]) / abs(y.v2[0]))
+             for x, y in zip(o32, o64)]
+    print("  FP32-FP64 relative divergence (step, length, v2_L):",
+          [(s_, f"{l:.1e}", f"{v:.1e}") for s_, l, v in curve[::8]], flush=True)
+    assert a.length == pytest.approx(b.length, rel=1e-3)
+    assert a.xi_w == pytest.approx(b.xi_w, rel=1e-3)
+    for k in range(3):
+        assert a.v2[k] == pytest.approx(b.v2[k], rel=1e-3), k
+    assert not math.isnan(b.xi_l) and a.xi_l == pytest.approx(b.xi_l, rel=1e-3)
