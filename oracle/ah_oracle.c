@@ -258,7 +258,8 @@ static double wrap_pi(double u)
 
 /* accumulators of one z-plane */
 enum { S_KIN, S_GRAD, S_ELEC, S_MAG, S_POT, S_LAG,
-       S_NUM_L, S_NUM_V, S_NUM_R, S_DEN_L, S_DEN_V, S_DEN_R, S_COUNT };
+       S_NUM_L, S_NUM_V, S_NUM_R, S_DEN_L, S_DEN_V, S_DEN_R,
+       S_PRES, S_PRES_L, S_RHO_L, S_COUNT };
 enum { I_W0, I_W1, I_W2, I_N0, I_N1, I_N2, I_PIERCED, I_NONFIN, I_COUNT };
 
 /*
@@ -270,6 +271,10 @@ enum { I_W0, I_W1, I_W2, I_N0, I_N1, I_N2, I_PIERCED, I_NONFIN, I_COUNT };
  *   L   = a^2 K - a^2 G + g (EE - BB) - h V
  *   rho = a^2 K + a^2 G + g (EE + BB) + h V.
  * <v^2>_X = 2R/(1+R), R = sum K X / sum G X, for X = L, V, rho.
+ * Pressure (one third of the trace of the stress tensor, the gauge part
+ * radiating with p = rho/3):  p = a^2 K - a^2 G / 3 + g (EE + BB) / 3 - h V;
+ * <v^2>_w = (1 + 3 p_L / rho_L) / 2 with p_L / rho_L = sum p L / sum rho L
+ * (Eq. (12), Lagrangian-weighted pressure and density).
  * Winding (Eq. (11)): theta = arg phi, Y_i = [theta^{x+i} - theta^x + A_i]_pi
  * - A_i, W_ij = rint((Y_i^x + Y_j^{x+i} - Y_i^{x+j} - Y_j^x) / 2pi).
  */
@@ -366,6 +371,7 @@ void or_measure(const or_params *p, int64_t n, const double *st, or_obs *obs,
 
                 double lag = a2 * K - a2 * G + g * (EE - BB) - h * V;
                 double rho = a2 * K + a2 * G + g * (EE + BB) + h * V;
+                double pres = a2 * K - a2 * G / 3.0 + g * (EE + BB) / 3.0 - h * V;
 
                 acc[S_KIN] += a2 * K;
                 acc[S_GRAD] += a2 * G;
@@ -379,6 +385,9 @@ void or_measure(const or_params *p, int64_t n, const double *st, or_obs *obs,
                 acc[S_DEN_L] += G * lag;
                 acc[S_DEN_V] += G * V;
                 acc[S_DEN_R] += G * rho;
+                acc[S_PRES] += pres;
+                acc[S_PRES_L] += pres * lag;
+                acc[S_RHO_L] += rho * lag;
             }
     }
 
@@ -415,6 +424,10 @@ void or_measure(const or_params *p, int64_t n, const double *st, or_obs *obs,
     obs->mag = dv * tot[S_MAG];
     obs->pot = dv * tot[S_POT];
     obs->energy = obs->kin + obs->grad + obs->elec + obs->mag + obs->pot;
+    obs->pres = dv * tot[S_PRES];
+    obs->pres_lag = dv * tot[S_PRES_L];
+    obs->rho_lag = dv * tot[S_RHO_L];
+    obs->v2_eos = 0.5 * (1.0 + 3.0 * obs->pres_lag / obs->rho_lag);
     for (int k = 0; k < 3; ++k) {
         obs->num[k] = dv * tot[S_NUM_L + k];
         obs->den[k] = dv * tot[S_DEN_L + k];

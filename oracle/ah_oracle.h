@@ -50,6 +50,9 @@ typedef struct {
     double sum_lag, xi_l;      /* dx^3 sum L ; a sqrt(-mu V_box / sum_lag)   */
     double num[3], den[3], v2[3];  /* weights X = L, V, rho                  */
     double kin, grad, elec, mag, pot, energy; /* dx^3-weighted parts of rho  */
+    double pres;               /* dx^3 sum p                                 */
+    double pres_lag, rho_lag;  /* dx^3 sum p L, dx^3 sum rho L               */
+    double v2_eos;             /* (1 + 3 pres_lag / rho_lag) / 2, Eq. (12)   */
     int64_t nonfinite;         /* sites with a non-finite field value        */
 } or_obs;
 

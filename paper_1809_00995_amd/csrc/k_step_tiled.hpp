@@ -401,15 +401,16 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
     }
 }
 
-// One realization: one block per tile.
+// One realization: one block per tile, tiles [tile0, tile0 + gridDim.x).
 template <typename T, int TY, int MODE>
 __global__ void __launch_bounds__(64 * TY)
-k_step_tiled(const RealDesc *descs, const Coef *coefs, int r, int cz, Slot *slot, int8_t *wind) {
+k_step_tiled(const RealDesc *descs, const Coef *coefs, int r, int cz, Slot *slot, int8_t *wind,
+             int tile0) {
     const RealDesc d = descs[r];
     const Coef c = coefs[r];
     if (MODE != MODE_MEASURE && !c.active)
         return;
-    tiled_tile<T, TY, MODE>(d, c, xcd_remap(blockIdx.x, gridDim.x), cz, slot, wind);
+    tiled_tile<T, TY, MODE>(d, c, tile0 + xcd_remap(blockIdx.x, gridDim.x), cz, slot, wind);
 }
 
 // A work item of the batched kernel: tile `tile` of realization r, with that
@@ -464,7 +465,7 @@ hipError_t launch_tiled_ty(const RealDesc *desc, const Coef *coef, int r, int nx
                            int cz, Slot *slot, int8_t *wind, hipStream_t stream) {
     const long blocks = (long)(nx / 64) * ((ny + TY - 1) / TY) * ((nz + cz - 1) / cz);
     hipLaunchKernelGGL((k_step_tiled<T, TY, MODE>), dim3((unsigned)blocks), dim3(64 * TY), 0,
-                       stream, desc, coef, r, cz, slot, wind);
+                       stream, desc, coef, r, cz, slot, wind, 0);
     return hipGetLastError();
 }
 

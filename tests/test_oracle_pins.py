@@ -386,3 +386,39 @@ def test_nonfinite_detection(O):
     st[I.EY, 2, 3, 4] = np.nan
     st[I.PHR, 0, 0, 1] = np.inf
     assert O.measure(p, 0, st).nonfinite == 2
+
+
+@pytest.mark.parametrize("era", [1.0, 2.0])
+def test_frw_continuity_pins_pressure(O, era):
+    """With the true equations of motion (s = 1) the box-averaged physical
+    energy density obeys the FRW continuity equation d(rho/a^4)/dtau =
+    -3 (a'/a) (rho + p)/a^4, i.e. for the conformal sums
+    d(sum rho)/dtau = (a'/a) sum (rho - 3 p).  Checked on the measured energy
+    and pressure (Eq. (12)); the half-step offset of the momenta gives an
+    O(dt) error, so dt is small."""
+    p = O.Params(8, 8, 8, dt=0.002, tau0=4.0, tau_ref=4.0, era_p=era, s=1.0)
+    st = I.smooth_state(8, seed=41, amp=0.4)
+    nsteps = 200
+    obs = []
+    for n in range(nsteps + 1):
+        obs.append(O.measure(p, n, st))
+        st = O.step(p, n, st)
+    tau = np.array([o.tau for o in obs])
+    a = np.array([_a(p, t) for t in tau])
+    rho = np.array([o.energy for o in obs])
+    pres = np.array([o.pres for o in obs])
+    kin = np.array([o.kin for o in obs])
+    elec = np.array([o.elec for o in obs])
+    # momenta averaged over the half steps around tau_n (second order in dt);
+    # the kinetic parts enter rho as kin + elec and p as kin + elec / 3
+    kraw = kin / a**2
+    kmid = a[:-1] ** 2 * 0.5 * (kraw[:-1] + kraw[1:])
+    emid = 0.5 * (elec[:-1] + elec[1:])          # g is constant for s = 1
+    rho_m = rho[:-1] - kin[:-1] - elec[:-1] + kmid + emid
+    pres_m = pres[:-1] - kin[:-1] - elec[:-1] / 3 + kmid + emid / 3
+    lhs = (rho_m[2:] - rho_m[:-2]) / (2 * p.dt)
+    rhs = era / tau[1:-2] * (rho_m[1:-1] - 3 * pres_m[1:-1])
+    assert np.abs(lhs - rhs).max() < 2e-3 * np.abs(rhs).max()
+    # the estimator of Eq. (12) as defined from the weighted sums
+    o = obs[-1]
+    assert o.v2_eos == pytest.approx(0.5 * (1 + 3 * o.pres_lag / o.rho_lag), rel=1e-14)
