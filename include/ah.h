@@ -108,6 +108,9 @@ typedef struct ah_obs {
     double num[3], den[3];   /* dx^3 sum K X, dx^3 sum G X for X = L, V, rho          */
     double v2[3];            /* <v^2>_X = 2R/(1+R), R = num/den, Eqs. (9)-(10)        */
     double kin, grad, elec, mag, pot, energy; /* dx^3 sums of the parts of rho      */
+    double pres;             /* dx^3 sum p, p = a^2 K - a^2 G/3 + g (EE + BB)/3 - h V */
+    double pres_lag, rho_lag;/* dx^3 sum p L, dx^3 sum rho L                          */
+    double v2_eos;           /* <v^2>_w = (1 + 3 pres_lag / rho_lag) / 2, Eq. (12)   */
     int64_t nonfinite;       /* sites holding a non-finite field value               */
 } ah_obs;
 

@@ -58,7 +58,8 @@ class _Obs(C.Structure):
                 ("num", C.c_double * 3), ("den", C.c_double * 3), ("v2", C.c_double * 3),
                 ("kin", C.c_double), ("grad", C.c_double), ("elec", C.c_double),
                 ("mag", C.c_double), ("pot", C.c_double), ("energy", C.c_double),
-                ("nonfinite", C.c_int64)]
+                ("pres", C.c_double), ("pres_lag", C.c_double), ("rho_lag", C.c_double),
+                ("v2_eos", C.c_double), ("nonfinite", C.c_int64)]
 
 
 _lib = None
@@ -152,6 +153,10 @@ class Obs:
     mag: float
     pot: float
     energy: float
+    pres: float
+    pres_lag: float
+    rho_lag: float
+    v2_eos: float
     nonfinite: int
 
     @staticmethod

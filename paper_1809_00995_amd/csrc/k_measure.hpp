@@ -24,6 +24,7 @@ __device__ __forceinline__ double wrap_pi(double u) {
 //   K = |Pi|^2, G = dx^-2 sum_i |e^{iA_i^x} phi^{x+i} - phi^x|^2, EE = dx^-2 sum_i E_i^2,
 //   BB = 2 dx^-4 sum_{xy,yz,zx} (1 - cos Xi), V = (|phi|^2 - sigma^2)^2 / 4,
 //   L = a^2 K - a^2 G + g (EE - BB) - h V, rho = a^2 K + a^2 G + g (EE + BB) + h V,
+//   p = a^2 K - a^2 G / 3 + g (EE + BB) / 3 - h V (one third of the stress trace),
 //   g = a^(2(1-s))/(2 e0^2), h = lambda0 a^(2+2s), a = a(tau_n);
 //   theta = arg phi, Y_i^x = [theta^{x+i} - theta^x + A_i^x]_pi - A_i^x,
 //   W_ij^x = rint((Y_i^x + Y_j^{x+i} - Y_i^{x+j} - Y_j^x) / 2 pi).
@@ -102,6 +103,7 @@ k_measure_plain(const RealDesc *descs, const Coef *coefs, int r, Slot *slot, int
         const double V = 0.25 * vv * vv;
         const double lag = a2 * K - a2 * G + g * (EE - BB) - h * V;
         const double rho = a2 * K + a2 * G + g * (EE + BB) + h * V;
+        const double pres = a2 * K - a2 * G / 3.0 + g * (EE + BB) / 3.0 - h * V;
 
         v[A_KIN] += a2 * K;
         v[A_GRAD] += a2 * G;
@@ -115,6 +117,9 @@ k_measure_plain(const RealDesc *descs, const Coef *coefs, int r, Slot *slot, int
         v[A_DEN_L] += G * lag;
         v[A_DEN_V] += G * V;
         v[A_DEN_R] += G * rho;
+        v[A_PRES] += pres;
+        v[A_PRES_L] += pres * lag;
+        v[A_RHO_L] += rho * lag;
 
         // winding, Eq. (11)
         auto arg = [&](int s) { return atan2((double)F[1][s], (double)F[0][s]); };
@@ -203,7 +208,7 @@ k_gauss(const RealDesc *descs, const Coef *coefs, int r, unsigned long long *out
 }
 
 // Observables of slot k (realization k % nreal) from the raw sums, in FP64
-// (Eqs. (9)-(11)): xi_L = a sqrt(-mu V_box / (dx^3 sum L)), mu = 2 pi sigma^2;
+// (Eqs. (9)-(12)): xi_L = a sqrt(-mu V_box / (dx^3 sum L)), mu = 2 pi sigma^2;
 // <v^2>_X = 2R/(1+R), R = sum K X / sum G X; length = (pi/6) dx sum |W|;
 // xi_W = sqrt(V_box / length).  Slots nobody measured get step = -1.
 __global__ void k_finalize(const RealDesc *descs, const Slot *slots, ah_obs *out, int nslots,
@@ -238,6 +243,10 @@ __global__ void k_finalize(const RealDesc *descs, const Slot *slots, ah_obs *out
     o.mag = dv * sl.acc.s[A_MAG];
     o.pot = dv * sl.acc.s[A_POT];
     o.energy = o.kin + o.grad + o.elec + o.mag + o.pot;
+    o.pres = dv * sl.acc.s[A_PRES];
+    o.pres_lag = dv * sl.acc.s[A_PRES_L];
+    o.rho_lag = dv * sl.acc.s[A_RHO_L];
+    o.v2_eos = 0.5 * (1.0 + 3.0 * o.pres_lag / o.rho_lag);   // Eq. (12)
     for (int i = 0; i < 3; ++i) {
         o.num[i] = dv * sl.acc.s[A_NUM_L + i];
         o.den[i] = dv * sl.acc.s[A_DEN_L + i];

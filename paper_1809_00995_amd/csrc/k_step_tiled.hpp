@@ -84,8 +84,8 @@ __device__ __forceinline__ T plaq_omc(T aic, T ais, T bjc, T bjs, T cic, T cis, 
 }
 
 // wrap count of a link: [u]_pi = u - 2 pi m (Eq. (11)), computed in FP64
-__device__ __forceinline__ long long wrap_count(double u) {
-    return (long long)floor((u + kPi) / kTwoPi);
+__device__ __forceinline__ int wrap_count(double u) {
+    return (int)floor((u + kPi) / kTwoPi);
 }
 
 template <typename T> struct SiteV {
@@ -153,13 +153,13 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
 
     // measurement constants and per-thread FP64 accumulators
     double msum[A_COUNT];
-    unsigned long long mcnt[C_COUNT];
+    int mcnt[C_COUNT];       // per thread at most 3 per plane of one column: 32 bits suffice
     double ma2 = 0.0, mg = 0.0, mh = 0.0, idx2 = 0.0;
     if (MEAS) {
         for (int k = 0; k < A_COUNT; ++k)
             msum[k] = 0.0;
         for (int k = 0; k < C_COUNT; ++k)
-            mcnt[k] = 0ull;
+            mcnt[k] = 0;
         ma2 = c.a_0 * c.a_0;
         mg = pow(c.a_0, 2.0 * (1.0 - d.s)) / (2.0 * d.e0 * d.e0);
         mh = d.lambda0 * pow(c.a_0, 2.0 + 2.0 * d.s);
@@ -309,15 +309,15 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
         }
 
         if (MEAS && owner) {
-            // Eqs. (9)-(11) for the site of S_n read above
+            // Eqs. (9)-(12) for the site of S_n read above
             const bool finite = isfinite((double)pr) && isfinite((double)pm) &&
                                 isfinite((double)pr0) && isfinite((double)pi0) &&
                                 isfinite((double)cur.ax) && isfinite((double)cur.ay) &&
                                 isfinite((double)cur.az) && isfinite((double)ex0) &&
                                 isfinite((double)ey0) && isfinite((double)ez0);
-            long long w3[3] = { 0, 0, 0 };
+            int w3[3] = { 0, 0, 0 };
             if (!finite) {
-                mcnt[C_NONFIN] += 1ull;
+                mcnt[C_NONFIN] += 1;
             } else {
                 const T gxr = cur.uxc * pr_xp - cur.uxs * pi_xp - pr;
                 const T gxi = cur.uxc * pi_xp + cur.uxs * pr_xp - pm;
@@ -337,6 +337,7 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
                 const double V = 0.25 * vv * vv;
                 const double lag = ma2 * K - ma2 * Gr + mg * (EE - BB) - mh * V;
                 const double rho = ma2 * K + ma2 * Gr + mg * (EE + BB) + mh * V;
+                const double pres = ma2 * K - ma2 * Gr / 3.0 + mg * (EE + BB) / 3.0 - mh * V;
                 msum[A_KIN] += ma2 * K;
                 msum[A_GRAD] += ma2 * Gr;
                 msum[A_ELEC] += mg * EE;
@@ -349,6 +350,9 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
                 msum[A_DEN_L] += Gr * lag;
                 msum[A_DEN_V] += Gr * V;
                 msum[A_DEN_R] += Gr * rho;
+                msum[A_PRES] += pres;
+                msum[A_PRES_L] += pres * lag;
+                msum[A_RHO_L] += rho * lag;
 
                 // winding (Eq. (11)) from link wrap counts
                 const double t0 = cur.th, t_xp = lth[cb][q + 1], t_yp = lth[cb][q + G::W];
@@ -358,22 +362,22 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
                 const double ay_xp = lar[cb][1][q + 1], az_xp = lar[cb][2][q + 1];
                 const double ax_yp = lar[cb][0][q + G::W], az_yp = lar[cb][2][q + G::W];
                 const double ax_zp = nxt.ax, ay_zp = nxt.ay;
-                const long long mx = wrap_count(t_xp - t0 + ax);
-                const long long my = wrap_count(t_yp - t0 + ay);
-                const long long mz = wrap_count(t_zp - t0 + az);
-                const long long my_xp = wrap_count(t_xpyp - t_xp + ay_xp);
-                const long long mx_yp = wrap_count(t_xpyp - t_yp + ax_yp);
-                const long long mz_yp = wrap_count(t_ypzp - t_yp + az_yp);
-                const long long my_zp = wrap_count(t_ypzp - t_zp + ay_zp);
-                const long long mx_zp = wrap_count(t_xpzp - t_zp + ax_zp);
-                const long long mz_xp = wrap_count(t_xpzp - t_xp + az_xp);
+                const int mx = wrap_count(t_xp - t0 + ax);
+                const int my = wrap_count(t_yp - t0 + ay);
+                const int mz = wrap_count(t_zp - t0 + az);
+                const int my_xp = wrap_count(t_xpyp - t_xp + ay_xp);
+                const int mx_yp = wrap_count(t_xpyp - t_yp + ax_yp);
+                const int mz_yp = wrap_count(t_ypzp - t_yp + az_yp);
+                const int my_zp = wrap_count(t_ypzp - t_zp + ay_zp);
+                const int mx_zp = wrap_count(t_xpzp - t_zp + ax_zp);
+                const int mz_xp = wrap_count(t_xpzp - t_xp + az_xp);
                 w3[0] = -(mx + my_xp - mx_yp - my);
                 w3[1] = -(my + mz_yp - my_zp - mz);
                 w3[2] = -(mz + mx_zp - mz_xp - mx);
                 for (int k = 0; k < 3; ++k) {
-                    mcnt[C_W0 + k] += (unsigned long long)w3[k];
-                    mcnt[C_N0 + k] += (unsigned long long)(w3[k] < 0 ? -w3[k] : w3[k]);
-                    mcnt[C_PIERCED] += w3[k] != 0 ? 1ull : 0ull;
+                    mcnt[C_W0 + k] += w3[k];
+                    mcnt[C_N0 + k] += w3[k] < 0 ? -w3[k] : w3[k];
+                    mcnt[C_PIERCED] += w3[k] != 0 ? 1 : 0;
                 }
             }
             if (MODE == MODE_MEASURE && wind)
@@ -396,7 +400,10 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
             slot->c = c;
             slot->measured = 1;
         }
-        block_accumulate<A_COUNT, C_COUNT, TY>(msum, mcnt, slot->acc.s, slot->acc.c);
+        unsigned long long cnt64[C_COUNT];
+        for (int k = 0; k < C_COUNT; ++k)
+            cnt64[k] = (unsigned long long)(long long)mcnt[k];   // two's complement for W sums
+        block_accumulate<A_COUNT, C_COUNT, TY>(msum, cnt64, slot->acc.s, slot->acc.c);
         __syncthreads();   // the reduction's LDS is reused by the next tile of a batch
     }
 }

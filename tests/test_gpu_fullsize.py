@@ -113,4 +113,5 @@ def test_config_256cubed_radiation_run(O):
     assert a.xi_w == pytest.approx(b.xi_w, rel=1e-3)
     for k in range(3):
         assert a.v2[k] == pytest.approx(b.v2[k], rel=1e-3), k
+    assert a.v2_eos == pytest.approx(b.v2_eos, rel=1e-3)
     assert not math.isnan(b.xi_l) and a.xi_l == pytest.approx(b.xi_l, rel=1e-3)

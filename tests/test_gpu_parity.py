@@ -94,13 +94,16 @@ def _compare_obs(g, o, rel):
     assert g.step == o.step
     assert g.n_wind_dir == o.n_wind_dir and g.net_wind_dir == o.net_wind_dir
     assert g.n_pierced == o.n_pierced and g.nonfinite == o.nonfinite == 0
-    for k in ("length", "sum_lag", "kin", "grad", "elec", "mag", "pot", "energy", "xi_w"):
+    for k in ("length", "sum_lag", "kin", "grad", "elec", "mag", "pot", "energy", "xi_w",
+              "pres", "pres_lag", "rho_lag"):
         assert getattr(g, k) == pytest.approx(getattr(o, k), rel=rel, abs=1e-300), k
     for k in ("num", "den"):
         # atol: sums of roundoff-sized terms (e.g. sum G V at |phi| = sigma) carry no digits
         assert np.allclose(getattr(g, k), getattr(o, k), rtol=rel, atol=1e-20), k
     for gv, ov in zip(g.v2, o.v2):
         assert (math.isnan(gv) and math.isnan(ov)) or gv == pytest.approx(ov, rel=rel, abs=1e-14)
+    assert (math.isnan(g.v2_eos) and math.isnan(o.v2_eos)) or \
+        g.v2_eos == pytest.approx(o.v2_eos, rel=rel, abs=1e-14)
     if math.isnan(o.xi_l):
         assert math.isnan(g.xi_l)
     else:
@@ -308,7 +311,8 @@ def test_fused_measurement_on_identical_input(O, prec):
     assert abs(g.n_wind - o.n_wind) <= amb
     if amb == 0:
         assert g.n_wind_dir == o.n_wind_dir
-    for k in ("kin", "grad", "elec", "mag", "pot", "energy", "sum_lag"):
+    for k in ("kin", "grad", "elec", "mag", "pot", "energy", "sum_lag", "pres", "pres_lag",
+              "rho_lag", "v2_eos"):
         assert getattr(g, k) == pytest.approx(getattr(o, k), rel=rel), k
     for k in ("num", "den", "v2"):
         assert np.allclose(getattr(g, k), getattr(o, k), rtol=rel * 10, atol=1e-20), k
