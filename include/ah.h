@@ -74,7 +74,8 @@ typedef struct ah_params {
     double dx, dt;        /* lattice spacing, conformal time step; dt/dx < 1/sqrt(3)     */
     double tau0, tau_ref; /* tau_n = tau0 + n dt; a(tau) = (max(tau,0)/tau_ref)^era_p    */
     double era_p;         /* 0 flat (a = 1), 1 radiation (a ~ tau), 2 matter (a ~ tau^2) */
-    double s;             /* 0 <= s <= 1: couplings e0 a^(s-1), lambda0 a^(2(s-1)), Eq. (8) */
+    double s;             /* -4 <= s <= 1: couplings e0 a^(s-1), lambda0 a^(2(s-1)), Eq. (8);
+                             s < 0 grows the comoving core; needs a(tau_step0) > 0     */
     double lambda0, e0, sigma; /* scalar coupling, gauge coupling, vacuum expectation   */
     uint64_t seed;        /* random-phase seed (AH_INIT_RANDOM_PHASE)                   */
     int32_t init;         /* AH_INIT_*                                                  */
@@ -82,6 +83,10 @@ typedef struct ah_params {
     int64_t step0;        /* step index n of the initial state (resume from step0)      */
     int64_t n_end;        /* 0: no limit; else the realization stops at S_{n_end} (its
                              tau_end): further steps leave it unchanged                 */
+    double s_late, tau_s; /* tau_s > 0: s(tau) = s before tau_s and s_late from tau_s on,
+                             e.g. a core-growth period (s < 0) followed by the true
+                             equations of motion (s_late = 1), Sec. 2 after Eq. (8);
+                             tau_s <= 0: s throughout                                   */
 } ah_params;
 
 /* Caller-owned device memory of one realization: 15 planes, see above.
@@ -125,8 +130,9 @@ const char *ah_last_error(const ah_ctx *ctx);
 /*
  * Create a context for n_real >= 1 independent realizations.  p[r] and buf[r]
  * describe realization r; all realizations share one precision.  Validates
- * the parameters (extents, alignment, CFL dt/dx < 1/sqrt(3), 0 <= s <= 1,
- * era_p >= 0, tau_ref > 0, a(tau_{step0 + 1/2}) > 0), allocates the scratch,
+ * the parameters (extents, alignment, CFL dt/dx < 1/sqrt(3), -4 <= s, s_late
+ * <= 1, era_p >= 0, tau_ref > 0, a(tau_{step0 + 1/2}) > 0, and a(tau_step0)
+ * > 0 when some s < 0), allocates the scratch,
  * then writes the initial state on the stream: the random-phase initial
  * condition of Sec. 2 (theta = 2 pi u - pi, u from SplitMix64 output number
  * idx+1 of generator p[r].seed), the vacuum, or nothing (AH_INIT_NONE: the

@@ -27,7 +27,7 @@ class _Params(C.Structure):
                 ("tau0", C.c_double), ("tau_ref", C.c_double),
                 ("era_p", C.c_double), ("s", C.c_double),
                 ("lambda0", C.c_double), ("e0", C.c_double), ("sigma", C.c_double),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("s_late", C.c_double), ("tau_s", C.c_double)]
 
 
 class _Coeffs(C.Structure):
@@ -64,11 +64,13 @@ class Params:
     e0: float = 1.0
     sigma: float = 1.0
     seed: int = 1
+    s_late: float = 1.0
+    tau_s: float = 0.0
 
     def _c(self) -> _Params:
         return _Params(self.nx, self.ny, self.nz, self.dx, self.dt, self.tau0,
                        self.tau_ref, self.era_p, self.s, self.lambda0, self.e0,
-                       self.sigma, self.seed & 0xFFFFFFFFFFFFFFFF)
+                       self.sigma, self.seed & 0xFFFFFFFFFFFFFFFF, self.s_late, self.tau_s)
 
     @property
     def shape(self):

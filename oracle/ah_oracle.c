@@ -16,7 +16,8 @@
  *    would break the discrete Gauss law;
  *  - couplings e = e0 a^(s-1), lambda = lambda0 a^(2(s-1)), Eq. (8), are
  *    substituted into Eqs. (4)-(5) and the ratios simplified so that no 0/0
- *    appears at a = 0 (pow(0,0) = 1);
+ *    appears at a = 0 (pow(0,0) = 1); s may change once, at tau_s (core
+ *    growth, then physical width), each coupling taking s at its own time;
  *  - scale factor a(tau) = (max(tau,0)/tau_ref)^p, p = 1 radiation, 2 matter,
  *    0 flat (the normalisation is not stated in Sec. 4);
  *  - magnetic energy (1/(e^2 dx^4)) sum_{i<j} (1 - cos Xi_ij), twice the
@@ -67,6 +68,14 @@ double or_scale_factor(const or_params *p, double tau)
     return pow(t / p->tau_ref, p->era_p);
 }
 
+/* The comoving-width parameter at time tau (Sec. 2, after Eq. (8)): s before
+ * tau_s and s_late from tau_s on when tau_s > 0 (a core-growth period
+ * followed by the true equations of motion); s throughout otherwise. */
+double or_s_of(const or_params *p, double tau)
+{
+    return (p->tau_s > 0.0 && tau >= p->tau_s) ? p->s_late : p->s;
+}
+
 /*
  * Coefficients of the staggered leapfrog, Sec. 2, Eqs. (4) and (5), with the
  * s-scaled couplings of Eq. (8):
@@ -87,6 +96,9 @@ void or_coefficients(const or_params *p, int64_t n, or_coeffs *c)
     double q = am / ap;
     double r = a0 / ap;
     double h = p->dt / (p->dx * p->dx);
+    double sm = or_s_of(p, tau - 0.5 * p->dt);
+    double s0 = or_s_of(p, tau);
+    double sp = or_s_of(p, tau + 0.5 * p->dt);
 
     c->tau = tau;
     c->a_m = am;
@@ -94,10 +106,14 @@ void or_coefficients(const or_params *p, int64_t n, or_coeffs *c)
     c->a_p = ap;
     c->c1 = q * q;
     c->c2 = h * r * r;
-    c->c3 = p->dt * 0.5 * p->lambda0 * r * r * pow(a0, 2.0 * p->s);
-    c->d1 = pow(q, 2.0 * (1.0 - p->s));
-    c->d2 = h * pow(r, 2.0 * (1.0 - p->s));
-    c->d3 = 2.0 * p->dt * p->e0 * p->e0 * r * r * pow(ap, 2.0 * p->s);
+    c->c3 = p->dt * 0.5 * p->lambda0 * r * r * pow(a0, 2.0 * s0);
+    /* (e_+/e_-)^2 and (e_+/e_0)^2; with s the same at both times they reduce
+     * to powers of the ratios q and r */
+    c->d1 = sm == sp ? pow(q, 2.0 * (1.0 - sp))
+                     : pow(am, 2.0 * (1.0 - sm)) * pow(ap, 2.0 * (sp - 1.0));
+    c->d2 = h * (s0 == sp ? pow(r, 2.0 * (1.0 - sp))
+                          : pow(a0, 2.0 * (1.0 - s0)) * pow(ap, 2.0 * (sp - 1.0)));
+    c->d3 = 2.0 * p->dt * p->e0 * p->e0 * r * r * pow(ap, 2.0 * sp);
 }
 
 /* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): the state advances by the
@@ -286,8 +302,9 @@ void or_measure(const or_params *p, int64_t n, const double *st, or_obs *obs,
     double tau = p->tau0 + (double)n * p->dt;
     double a = or_scale_factor(p, tau);
     double a2 = a * a;
-    double g = pow(a, 2.0 * (1.0 - p->s)) / (2.0 * p->e0 * p->e0);
-    double h = p->lambda0 * pow(a, 2.0 + 2.0 * p->s);
+    double sn = or_s_of(p, tau);
+    double g = pow(a, 2.0 * (1.0 - sn)) / (2.0 * p->e0 * p->e0);
+    double h = p->lambda0 * pow(a, 2.0 + 2.0 * sn);
     double idx2 = 1.0 / (p->dx * p->dx);
     double dv = p->dx * p->dx * p->dx;
     double s2 = p->sigma * p->sigma;
@@ -455,7 +472,7 @@ void or_gauss(const or_params *p, int64_t n, const double *st, double *max_abs,
     int nz = p->nz;
     double tau = p->tau0 + (double)n * p->dt;
     double am = or_scale_factor(p, tau - 0.5 * p->dt);
-    double fe = pow(am, 2.0 * (1.0 - p->s)) / (p->e0 * p->e0);
+    double fe = pow(am, 2.0 * (1.0 - or_s_of(p, tau - 0.5 * p->dt))) / (p->e0 * p->e0);
     double fp = 2.0 * p->dx * p->dx * am * am;
     double *pmax = calloc((size_t)nz, sizeof(double));
     double *psq = calloc((size_t)nz, sizeof(double));

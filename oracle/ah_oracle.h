@@ -31,6 +31,7 @@ typedef struct {
     double s;               /* comoving-width parameter, Eq. (8)                */
     double lambda0, e0, sigma;
     uint64_t seed;
+    double s_late, tau_s;   /* s(tau) = s_late for tau >= tau_s when tau_s > 0 */
 } or_params;
 
 typedef struct {
@@ -57,6 +58,7 @@ typedef struct {
 } or_obs;
 
 double or_scale_factor(const or_params *p, double tau);
+double or_s_of(const or_params *p, double tau);
 void or_coefficients(const or_params *p, int64_t n, or_coeffs *c);
 
 /* k-th output (k >= 1) of the SplitMix64 generator seeded with `seed`. */

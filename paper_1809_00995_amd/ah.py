@@ -42,7 +42,8 @@ class _Params(C.Structure):
                 ("era_p", C.c_double), ("s", C.c_double),
                 ("lambda0", C.c_double), ("e0", C.c_double), ("sigma", C.c_double),
                 ("seed", C.c_uint64), ("init", C.c_int32), ("reserved", C.c_int32),
-                ("step0", C.c_int64), ("n_end", C.c_int64)]
+                ("step0", C.c_int64), ("n_end", C.c_int64),
+                ("s_late", C.c_double), ("tau_s", C.c_double)]
 
 
 class _Buffers(C.Structure):
@@ -116,11 +117,14 @@ class Params:
     init: int = AH_INIT_RANDOM_PHASE
     step0: int = 0
     n_end: int = 0
+    s_late: float = 1.0
+    tau_s: float = 0.0
 
     def _c(self) -> _Params:
         return _Params(self.nx, self.ny, self.nz, self.precision, self.dx, self.dt, self.tau0,
                        self.tau_ref, self.era_p, self.s, self.lambda0, self.e0, self.sigma,
-                       self.seed & 0xFFFFFFFFFFFFFFFF, self.init, 0, self.step0, self.n_end)
+                       self.seed & 0xFFFFFFFFFFFFFFFF, self.init, 0, self.step0, self.n_end,
+                       self.s_late, self.tau_s)
 
     @property
     def dtype(self):

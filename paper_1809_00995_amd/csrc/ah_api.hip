@@ -112,8 +112,13 @@ int validate(const ah_params &q, int r, const ah_buffers &b, int prec) {
         return bad(AH_E_INVALID, "dx and dt must be positive and finite");
     if (!(q.dt / q.dx < 1.0 / std::sqrt(3.0)))
         return bad(AH_E_DOMAIN, "CFL condition dt/dx < 1/sqrt(3) violated");
-    if (!(q.s >= 0.0 && q.s <= 1.0))
-        return bad(AH_E_DOMAIN, "s must lie in [0, 1]");
+    if (!(q.s >= -4.0 && q.s <= 1.0))
+        return bad(AH_E_DOMAIN, "s must lie in [-4, 1]");
+    if (!std::isfinite(q.tau_s) || (q.tau_s > 0.0 && !(q.s_late >= -4.0 && q.s_late <= 1.0)))
+        return bad(AH_E_DOMAIN, "s_late must lie in [-4, 1] and tau_s be finite");
+    const bool growth = q.s < 0.0 || (q.tau_s > 0.0 && q.s_late < 0.0);
+    if (growth && !(scale_factor_host(q, q.tau0 + (double)q.step0 * q.dt) > 0.0))
+        return bad(AH_E_DOMAIN, "s < 0 needs a(tau_step0) > 0");
     if (!(q.era_p >= 0.0) || !std::isfinite(q.era_p))
         return bad(AH_E_DOMAIN, "era_p must be >= 0");
     if (!(q.tau_ref > 0.0) || !std::isfinite(q.tau_ref) || !std::isfinite(q.tau0))
@@ -463,6 +468,8 @@ int ah_init(ah_ctx **out, int32_t n_real, const ah_params *p, const ah_buffers *
         d.sigma = q.sigma;
         d.step0 = q.step0;
         d.n_end = q.n_end;
+        d.s_late = q.s_late;
+        d.tau_s = q.tau_s;
         c->step[r] = q.step0;
     }
 

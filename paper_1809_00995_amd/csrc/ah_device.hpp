@@ -27,6 +27,7 @@ struct RealDesc {
     int64_t N;             // nx * ny * nz
     double dx, dt, tau0, tau_ref, era_p, s, lambda0, e0, sigma;
     int64_t step0, n_end;
+    double s_late, tau_s;  // s(tau) = s_late from tau_s on when tau_s > 0
 };
 
 // FP64 bookkeeping for advancing realization r from S_n (written on the
@@ -36,6 +37,7 @@ struct Coef {
     int32_t active;        // 0 once the realization has reached n_end
     int32_t parity;        // 0: phi, A in planes 0,1,4-6; 1: in planes 10-14
     double tau, a_m, a_0, a_p;
+    double s_m, s_0;       // comoving-width parameter at tau_{n-1/2}, tau_n
     double c1, c2, c3;     // Pi update, Eq. (4)
     double d1, d2, d3;     // E update, Eq. (5)
 };

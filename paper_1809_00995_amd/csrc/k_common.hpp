@@ -12,12 +12,20 @@ __device__ __forceinline__ double scale_factor(const RealDesc &d, double tau) {
     return pow(t / d.tau_ref, d.era_p);
 }
 
+// s(tau) of Eq. (8): a core-growth value s until tau_s, then s_late (when tau_s > 0).
+__device__ __forceinline__ double s_at(const RealDesc &d, double tau) {
+    return (d.tau_s > 0.0 && tau >= d.tau_s) ? d.s_late : d.s;
+}
+
 // FP64 bookkeeping of Eqs. (4), (5) and (8), one thread per realization.
 // Substituting e = e0 a^(s-1) and lambda = lambda0 a^(2(s-1)) into the
 // coefficients of Eqs. (4)-(5) and cancelling powers of a gives forms that
 // stay finite at a(tau0) = 0:
 //   c1 = (a_-/a_+)^2, c2 = dt/dx^2 (a_0/a_+)^2, c3 = dt lambda0/2 (a_0/a_+)^2 a_0^(2s),
 //   d1 = (a_-/a_+)^(2(1-s)), d2 = dt/dx^2 (a_0/a_+)^(2(1-s)), d3 = 2 dt e0^2 (a_0/a_+)^2 a_+^(2s).
+// When s changes between the three times of a step (core growth ending),
+// each coupling takes s at its own time: d1 = (e_+/e_-)^2 =
+// a_-^(2(1-s_-)) a_+^(2(s_+-1)), d2 = dt/dx^2 a_0^(2(1-s_0)) a_+^(2(s_+-1)).
 // With advance != 0 the realization's step counter moves on to n+1 (the
 // coefficients describe the update of S_n); frozen realizations stay.
 __global__ void k_bookkeep(const RealDesc *desc, int64_t *step, Coef *coef, int nreal,
@@ -37,12 +45,17 @@ __global__ void k_bookkeep(const RealDesc *desc, int64_t *step, Coef *coef, int 
     c.a_p = scale_factor(d, c.tau + 0.5 * d.dt);
     const double q = c.a_m / c.a_p, rr = c.a_0 / c.a_p;
     const double h = d.dt / (d.dx * d.dx);
+    c.s_m = s_at(d, c.tau - 0.5 * d.dt);
+    c.s_0 = s_at(d, c.tau);
+    const double s_p = s_at(d, c.tau + 0.5 * d.dt);
     c.c1 = q * q;
     c.c2 = h * rr * rr;
-    c.c3 = d.dt * 0.5 * d.lambda0 * rr * rr * pow(c.a_0, 2.0 * d.s);
-    c.d1 = pow(q, 2.0 * (1.0 - d.s));
-    c.d2 = h * pow(rr, 2.0 * (1.0 - d.s));
-    c.d3 = 2.0 * d.dt * d.e0 * d.e0 * rr * rr * pow(c.a_p, 2.0 * d.s);
+    c.c3 = d.dt * 0.5 * d.lambda0 * rr * rr * pow(c.a_0, 2.0 * c.s_0);
+    c.d1 = c.s_m == s_p ? pow(q, 2.0 * (1.0 - s_p))
+                        : pow(c.a_m, 2.0 * (1.0 - c.s_m)) * pow(c.a_p, 2.0 * (s_p - 1.0));
+    c.d2 = h * (c.s_0 == s_p ? pow(rr, 2.0 * (1.0 - s_p))
+                             : pow(c.a_0, 2.0 * (1.0 - c.s_0)) * pow(c.a_p, 2.0 * (s_p - 1.0)));
+    c.d3 = 2.0 * d.dt * d.e0 * d.e0 * rr * rr * pow(c.a_p, 2.0 * s_p);
     coef[r] = c;
     if (advance && c.active)
         step[r] = n + 1;

@@ -39,8 +39,8 @@ k_measure_plain(const RealDesc *descs, const Coef *coefs, int r, Slot *slot, int
     for (int f = 0; f < 10; ++f)
         F[f] = plane<T>(d, field_plane(f, par));
     const double a = c.a_0, a2 = a * a;
-    const double g = pow(a, 2.0 * (1.0 - d.s)) / (2.0 * d.e0 * d.e0);
-    const double h = d.lambda0 * pow(a, 2.0 + 2.0 * d.s);
+    const double g = pow(a, 2.0 * (1.0 - c.s_0)) / (2.0 * d.e0 * d.e0);
+    const double h = d.lambda0 * pow(a, 2.0 + 2.0 * c.s_0);
     const double idx2 = 1.0 / (d.dx * d.dx), s2 = d.sigma * d.sigma;
 
     double v[A_COUNT];
@@ -169,7 +169,7 @@ k_gauss(const RealDesc *descs, const Coef *coefs, int r, unsigned long long *out
     const T *phr = plane<T>(d, field_plane(0, par)), *phi = plane<T>(d, field_plane(1, par));
     const T *pir = plane<T>(d, P_PIR), *pii = plane<T>(d, P_PII);
     const T *E[3] = { plane<T>(d, P_EX), plane<T>(d, P_EX + 1), plane<T>(d, P_EX + 2) };
-    const double fe = pow(c.a_m, 2.0 * (1.0 - d.s)) / (d.e0 * d.e0);
+    const double fe = pow(c.a_m, 2.0 * (1.0 - c.s_m)) / (d.e0 * d.e0);
     const double fp = 2.0 * d.dx * d.dx * c.a_m * c.a_m;
     double mx = 0.0, sq = 0.0;
     for (int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < d.N;

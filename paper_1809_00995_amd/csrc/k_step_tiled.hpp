@@ -161,8 +161,8 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
         for (int k = 0; k < C_COUNT; ++k)
             mcnt[k] = 0;
         ma2 = c.a_0 * c.a_0;
-        mg = pow(c.a_0, 2.0 * (1.0 - d.s)) / (2.0 * d.e0 * d.e0);
-        mh = d.lambda0 * pow(c.a_0, 2.0 + 2.0 * d.s);
+        mg = pow(c.a_0, 2.0 * (1.0 - c.s_0)) / (2.0 * d.e0 * d.e0);
+        mh = d.lambda0 * pow(c.a_0, 2.0 + 2.0 * c.s_0);
         idx2 = 1.0 / (d.dx * d.dx);
     }
 
@@ -228,7 +228,10 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
         const int cb = (z - z0) & 1, nb_ = cb ^ 1;
         const int zp = z + 1 == nz ? 0 : z + 1;
         const int s = own(z);
-        const T pr0 = pir[s], pi0 = pii[s], ex0 = E0[s], ey0 = E1[s], ez0 = E2[s];
+        // the momenta are read once, by this thread only: streaming loads
+        const T pr0 = __builtin_nontemporal_load(pir + s), pi0 = __builtin_nontemporal_load(pii + s);
+        const T ex0 = __builtin_nontemporal_load(E0 + s), ey0 = __builtin_nontemporal_load(E1 + s);
+        const T ez0 = __builtin_nontemporal_load(E2 + s);
         load_site(own(zp), nxt);
         put(nb_, q, nxt);
         stage_halo(nb_, zp);
@@ -295,16 +298,17 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
             const T enz = d1 * ez0 + d3 * jz - d2 * curl_z;
 
             if (owner) {
-                pir[s] = pnr;
-                pii[s] = pni;
-                E0[s] = enx;
-                E1[s] = eny;
-                E2[s] = enz;
-                ophr[s] = pr + dt * pnr;          // Eq. (6)
-                ophi[s] = pm + dt * pni;
-                oA0[s] = cur.ax + dt * enx;       // Eq. (7)
-                oA1[s] = cur.ay + dt * eny;
-                oA2[s] = cur.az + dt * enz;
+                // streaming stores: the new state is not read again in this launch
+                __builtin_nontemporal_store(pnr, pir + s);
+                __builtin_nontemporal_store(pni, pii + s);
+                __builtin_nontemporal_store(enx, E0 + s);
+                __builtin_nontemporal_store(eny, E1 + s);
+                __builtin_nontemporal_store(enz, E2 + s);
+                __builtin_nontemporal_store((T)(pr + dt * pnr), ophr + s);        // Eq. (6)
+                __builtin_nontemporal_store((T)(pm + dt * pni), ophi + s);
+                __builtin_nontemporal_store((T)(cur.ax + dt * enx), oA0 + s);    // Eq. (7)
+                __builtin_nontemporal_store((T)(cur.ay + dt * eny), oA1 + s);
+                __builtin_nontemporal_store((T)(cur.az + dt * enz), oA2 + s);
             }
         }
 

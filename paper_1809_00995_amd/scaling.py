@@ -1,0 +1,104 @@
+"""Scaling validation of string networks (Sec. 4 and Table 3 of arXiv:1809.00995).
+
+Evolves seeded random-phase lattices to half a light-crossing time with the
+HIP library (FP32 fields, FP64 diagnostics) and reports, per case, the slopes
+dxi/dtau of the Lagrangian and winding string separations and the mean of
+the velocity estimators over the late, scaling part of the run, averaged
+over seeds with their standard error.  Cases follow Table 3: radiation era
+with s = 1 and s = 0, matter era with s = 0, and radiation with a core-growth
+period (s = -1) before the true equations of motion (s = 1).
+
+    python -m paper_1809_00995_amd.scaling --n 512 --seeds 5 --out scaling.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+
+import numpy as np
+import torch
+
+from . import ah as AH
+
+# name: (era p, s, core growth).  With core growth the run starts at tau = 0.1 tau_end with
+# s = -1 and switches to s = 1 at tau_cg = tau_end / 2, where a = 1 (the couplings are
+# continuous there); otherwise a(tau_end) = 1 and the run starts at tau = 0.
+CASES = {"radiation_s1": (1.0, 1.0, False), "radiation_s0": (1.0, 0.0, False),
+         "matter_s0": (2.0, 0.0, False), "radiation_s1_core_growth": (1.0, 1.0, True)}
+
+
+def evolve(n: int, era: float, s: float, seed: int, measure_every: int = 10, dx: float = 0.5,
+           dt: float = 0.1, core_growth: bool = False):
+    """One run to tau_end = n dx / 2; returns the observation series."""
+    tau_end = n * dx / 2.0
+    if core_growth:
+        tau0 = round(0.1 * tau_end / dt) * dt
+        p = AH.Params(n, n, n, precision=AH.AH_FP32, dx=dx, dt=dt, tau0=tau0,
+                      tau_ref=tau_end / 2, era_p=era, s=-1.0, s_late=s, tau_s=tau_end / 2,
+                      seed=seed)
+    else:
+        tau0 = 0.0
+        p = AH.Params(n, n, n, precision=AH.AH_FP32, dx=dx, dt=dt, tau0=0.0, tau_ref=tau_end,
+                      era_p=era, s=s, seed=seed)
+    steps = int(round((tau_end - tau0) / dt))
+    with AH.Context([p], [AH.alloc_planes(p)]) as c:
+        obs = [o[0] for o in c.step(steps, measure_every=measure_every)]
+        obs += c.measure()
+    torch.cuda.empty_cache()
+    return obs
+
+
+def fit(obs, frac_start: float = 0.5):
+    """Slopes of xi_L and xi_W against tau, and mean velocity estimators, over
+    tau >= frac_start * tau_end."""
+    tau_end = obs[-1].tau
+    late = [o for o in obs if o.tau >= frac_start * tau_end]
+    tau = np.array([o.tau for o in late])
+    out = {}
+    for key in ("xi_l", "xi_w"):
+        xi = np.array([getattr(o, key) for o in late])
+        ok = np.isfinite(xi)
+        out["dxi_" + key[3:]] = float(np.polyfit(tau[ok], xi[ok], 1)[0]) if ok.sum() > 2 else math.nan
+    out["v2_V"] = float(np.mean([o.v2[1] for o in late]))
+    out["v2_L"] = float(np.mean([o.v2[0] for o in late]))
+    out["v2_w"] = float(np.mean([o.v2_eos for o in late]))
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--seeds", type=int, default=5)
+    ap.add_argument("--cases", default=",".join(CASES))
+    ap.add_argument("--measure-every", type=int, default=10)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    result = {"n": args.n, "seeds": args.seeds, "cases": {}}
+    for name in args.cases.split(","):
+        era, s, cg = CASES[name]
+        runs = []
+        for k in range(args.seeds):
+            obs = evolve(args.n, era, s, seed=100 + k, measure_every=args.measure_every,
+                         core_growth=cg)
+            runs.append(fit(obs))
+            print(f"{name} seed {100 + k}: " + ", ".join(f"{a}={b:.4f}" for a, b in runs[-1].items()),
+                  flush=True)
+        summary = {}
+        for key in runs[0]:
+            vals = np.array([r[key] for r in runs])
+            summary[key] = {"mean": float(np.mean(vals)),
+                            "stderr": float(np.std(vals, ddof=1) / math.sqrt(len(vals)))
+                            if len(vals) > 1 else math.nan}
+        result["cases"][name] = {"runs": runs, "summary": summary}
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(result, f, indent=1)
+    print(json.dumps({k: {q: round(v["mean"], 4) for q, v in c["summary"].items()}
+                      for k, c in result["cases"].items()}), flush=True)
+    return result
+
+
+if __name__ == "__main__":
+    sys.exit(0 if main() else 1)

@@ -12,7 +12,8 @@ GROUPS = {"phi": [0, 1], "pi": [2, 3], "a": [4, 5, 6], "e": [7, 8, 9]}
 
 def oracle_params(O, p: "AH.Params"):
     return O.Params(p.nx, p.ny, p.nz, dx=p.dx, dt=p.dt, tau0=p.tau0, tau_ref=p.tau_ref,
-                    era_p=p.era_p, s=p.s, lambda0=p.lambda0, e0=p.e0, sigma=p.sigma, seed=p.seed)
+                    era_p=p.era_p, s=p.s, lambda0=p.lambda0, e0=p.e0, sigma=p.sigma, seed=p.seed,
+                    s_late=p.s_late, tau_s=p.tau_s)
 
 
 def upload(p: "AH.Params", st: np.ndarray) -> torch.Tensor:

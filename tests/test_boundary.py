@@ -62,6 +62,9 @@ def _init(**kw):
 @pytest.mark.parametrize("kw,code,text", [
     (dict(dt=0.3), B.AH_E_DOMAIN, "CFL"),
     (dict(s=1.5), B.AH_E_DOMAIN, "s must"),
+    (dict(s=-5.0), B.AH_E_DOMAIN, "s must"),
+    (dict(s=-1.0, tau0=0.0), B.AH_E_DOMAIN, "s < 0"),
+    (dict(tau_s=2.0, s_late=3.0), B.AH_E_DOMAIN, "s_late"),
     (dict(era_p=-1.0), B.AH_E_DOMAIN, "era_p"),
     (dict(tau_ref=0.0), B.AH_E_DOMAIN, "tau_ref"),
     (dict(tau0=-5.0), B.AH_E_DOMAIN, "a(tau"),

@@ -422,3 +422,71 @@ def test_frw_continuity_pins_pressure(O, era):
     # the estimator of Eq. (12) as defined from the weighted sums
     o = obs[-1]
     assert o.v2_eos == pytest.approx(0.5 * (1 + 3 * o.pres_lag / o.rho_lag), rel=1e-14)
+
+
+# ------------------------- core growth: s changes at tau_s (Sec. 2, after Eq. (8)) ----
+
+@pytest.mark.parametrize("era", [1.0, 2.0])
+def test_core_growth_switch_keeps_gauss_law(O, era):
+    """s = -1 (core growth) until tau_s, then s = 1: the Gauss residual of an
+    arbitrary state stays constant site by site through the switch."""
+    p = O.Params(7, 6, 5, tau0=1.0, tau_ref=3.0, era_p=era, s=-1.0, s_late=1.0, tau_s=2.0)
+    st = I.random_state((7, 6, 5), seed=17)
+    _, _, g0 = O.gauss(p, 0, st, site_map=True)
+    assert np.abs(g0).max() > 1e-3
+    for n in range(25):                       # tau from 1.0 to 3.5 crosses tau_s = 2
+        st = O.step(p, n, st)
+        _, _, g = O.gauss(p, n + 1, st, site_map=True)
+        assert np.abs(g - g0).max() < 1e-12 * max(1.0, np.abs(g0).max())
+
+
+def test_core_growth_uniform_fields_match_ode(O):
+    """Uniform phi = f and A_j across the switch of s at tau_s.  In canonical
+    momenta P_f = a^2 f' and P_A = A'/e^2, which stay continuous when the
+    couplings e = e0 a^(s-1), lambda = lambda0 a^(2(s-1)) jump:
+        f' = P_f / a^2,   P_f' = a^2 (2f/dx^2) sum (cos A - 1) - (lambda0/2) a^(2+2s) (f^2 - 1) f
+        A' = e0^2 a^(2(s-1)) P_A,   P_A' = -2 a^2 f^2 sin A
+    integrated piecewise by RK; the leapfrog agrees to O(dt)."""
+    p = O.Params(4, 4, 4, dt=0.001, tau0=2.0, tau_ref=2.0, era_p=1.0, s=-1.0, s_late=1.0,
+                 tau_s=2.25)
+    e0 = p.e0
+
+    def rhs_for(s):
+        def rhs(tau, y):
+            f, pf, A, pA = y[0], y[1], y[2:5], y[5:8]
+            a = _a(p, tau)
+            df = pf / a**2
+            dpf = (a**2 * 2 * f / p.dx**2 * np.sum(np.cos(A) - 1)
+                   - 0.5 * p.lambda0 * a ** (2 + 2 * s) * (f * f - p.sigma**2) * f)
+            dA = e0**2 * a ** (2 * (s - 1)) * pA
+            dpA = -2 * a**2 * f * f * np.sin(A)
+            return np.concatenate(([df, dpf], dA, dpA))
+        return rhs
+
+    f0, u0 = 1.2, 0.1
+    A0 = np.array([0.3, -0.5, 0.8])
+    w0 = np.array([0.2, 0.1, -0.3])
+    a0 = _a(p, p.tau0)
+    e_0 = e0 * a0 ** (p.s - 1)
+    y0 = np.concatenate(([f0, a0**2 * u0], A0, w0 / e_0**2))
+    # momenta at tau0 - dt/2 for the staggered start
+    back = solve_ivp(rhs_for(p.s), (p.tau0, p.tau0 - 0.5 * p.dt), y0, rtol=1e-12, atol=1e-14).y[:, -1]
+    am = _a(p, p.tau0 - 0.5 * p.dt)
+    em = e0 * am ** (p.s - 1)
+    st = np.zeros(p.shape)
+    st[I.PHR] = f0
+    st[I.PIR] = back[1] / am**2
+    for j in range(3):
+        st[I.AX + j] = A0[j]
+        st[I.EX + j] = back[5 + j] * em**2
+    nsteps = 500                              # tau 2.0 -> 2.5 across tau_s = 2.25
+    st, _ = O.run(p, st, 0, nsteps)
+    tau_end = p.tau0 + nsteps * p.dt
+    mid = solve_ivp(rhs_for(p.s), (p.tau0, p.tau_s), y0, rtol=1e-12, atol=1e-14).y[:, -1]
+    fin = solve_ivp(rhs_for(p.s_late), (p.tau_s, tau_end), mid, rtol=1e-12, atol=1e-14).y[:, -1]
+    assert abs(st[I.PHR, 0, 0, 0] - fin[0]) < 2e-3
+    for j in range(3):
+        assert abs(st[I.AX + j, 0, 0, 0] - fin[2 + j]) < 2e-3
+    # and the switch matters at this size: the constant-s solution is far away
+    const = solve_ivp(rhs_for(p.s), (p.tau0, tau_end), y0, rtol=1e-12, atol=1e-14).y[:, -1]
+    assert max(abs(const[2 + j] - fin[2 + j]) for j in range(3)) > 2e-2
