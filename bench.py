@@ -9,10 +9,12 @@ one leapfrog step of the whole lattice (Eqs. (4)-(7)), with the diagnostics
 of Eqs. (9)-(11) on the steps the cadence selects.
 
 Prints ONE JSON line: FP32 storage and arithmetic (FP64 bookkeeping and
-reductions) is the headline ``value``; the FP64 kernel and the plain FP64
-kernel are reported beside it.  ``roofline`` is for the dominant kernel (the
-step kernel) from HIP events around single-step calls; ``cpu_baseline`` times
-the FP64 CPU oracle on a bounded sample on this host.
+reductions) is the headline ``value``, in the 20-plane layout where unmeasured
+steps go in pairs through the two-steps-per-pass kernel (``--layout 15``: one
+step per pass).  The other layout, the FP64 kernels and the plain FP64 kernel
+are reported beside it.  ``roofline`` is for the dominant kernel (the step
+kernel) from HIP events around calls that run exactly one launch of it;
+``cpu_baseline`` times the FP64 CPU oracle on a bounded sample on this host.
 """
 from __future__ import annotations
 
@@ -41,19 +43,24 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-secondary", action="store_true", help="FP32 headline only")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble")
-    ap.add_argument("--kernel", default="auto", choices=["auto", "plain", "tiled"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "plain", "tiled", "tiled2"])
+    ap.add_argument("--layout", type=int, default=20, choices=[15, 20],
+                    help="field planes: 20 lets unmeasured steps go two per pass (default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for the "
                          "HBM byte counters of a profiler run)")
     return ap.parse_args()
 
 
-def run_form(AH, torch, n, prec, kernel, steps, warmup):
+def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15):
     """Time `steps` steps (with the measurement cadence) after `warmup` steps.
-    Returns (site-updates/s, ms/step, mean step-kernel ms)."""
+    Returns (site-updates/s, ms/step, mean step-kernel ms per launch, steps per
+    launch, last observation)."""
     # tau_end = n dx / 2, half a light-crossing time (Sec. 2), with a(tau_end) = 1
     p = AH.Params(n, n, n, precision=prec, dx=0.5, dt=0.1, tau0=0.0, tau_ref=n * 0.5 / 2.0,
-                  era_p=2.0, s=0.0, seed=2024)
+                  era_p=2.0, s=0.0, seed=2024,
+                  layout=AH.AH_LAYOUT_20 if layout == 20 else AH.AH_LAYOUT_15)
+    two = layout == 20 and kernel in (AH.AH_KERNEL_AUTO, AH.AH_KERNEL_TILED2)
     planes = AH.alloc_planes(p)
     ctx = AH.Context([p], [planes])
     if kernel != AH.AH_KERNEL_AUTO:
@@ -72,13 +79,15 @@ def run_form(AH, torch, n, prec, kernel, steps, warmup):
     ms = t0.elapsed_time(t1)
     rate = n ** 3 * steps / (ms * 1e-3)
 
-    # dominant kernel: single-step calls bracketed by events on the same stream
+    # dominant kernel: calls that run one launch of it (one pass: one step, or
+    # a pair with the two-step kernel), bracketed by events on the same stream
+    per = 2 if two else 1
     k = max(5, min(steps, 20))
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(k)]
     for a, b in evs:
         a.record(stream)
-        ctx.step(1)
+        ctx.step(per)
         b.record(stream)
     torch.cuda.synchronize()
     kms = sum(a.elapsed_time(b) for a, b in evs) / k
@@ -86,7 +95,7 @@ def run_form(AH, torch, n, prec, kernel, steps, warmup):
     ctx.close()
     del planes
     torch.cuda.empty_cache()
-    return rate, ms / steps, kms, last
+    return rate, ms / steps, kms, per, last
 
 
 def ensemble_params(AH):
@@ -156,13 +165,17 @@ def main():
     import torch
     import paper_1809_00995_amd as AH
     kern = {"auto": AH.AH_KERNEL_AUTO, "plain": AH.AH_KERNEL_PLAIN,
-            "tiled": AH.AH_KERNEL_TILED}[args.kernel]
+            "tiled": AH.AH_KERNEL_TILED, "tiled2": AH.AH_KERNEL_TILED2}[args.kernel]
     n, K, W = args.n, args.steps, args.warmup
+    other = 15 if args.layout == 20 else 20
 
-    rate32, ms32, kms32, last32 = run_form(AH, torch, n, AH.AH_FP32, kern, K, W)
-    print(f"# fp32 {args.kernel}: {rate32:.4g} site-updates/s, {ms32:.3f} ms/step, "
-          f"step kernel {kms32:.3f} ms", file=sys.stderr, flush=True)
-    achieved = BYTES_PER_SITE["f32"] * n ** 3 / (kms32 * 1e-3) / 1e9
+    rate32, ms32, kms32, per32, last32 = run_form(AH, torch, n, AH.AH_FP32, kern, K, W,
+                                                  args.layout)
+    print(f"# fp32 {args.kernel} layout {args.layout}: {rate32:.4g} site-updates/s, "
+          f"{ms32:.3f} ms/step, step kernel {kms32:.3f} ms per {per32}-step launch",
+          file=sys.stderr, flush=True)
+    achieved = BYTES_PER_SITE["f32"] * n ** 3 * per32 / (kms32 * 1e-3) / 1e9
+    kname = "two-steps-per-pass kernel" if per32 == 2 else "step kernel"
     line = {
         "metric": "lattice site-updates/s and % HBM roofline, FP32 vs FP64 kernel, 512^3",
         "value": rate32, "unit": "site-updates/s", "n_gpus": 1, "steps": K, "warmup": W,
@@ -172,28 +185,34 @@ def main():
                                f"e0=1, sigma=1, dx=0.5, dt=0.1, random-phase init, string "
                                f"length and <v^2> every {MEASURE_EVERY} steps",
                    "lattice": [n, n, n], "measure_every": MEASURE_EVERY, "kernel": args.kernel,
+                   "layout": args.layout,
                    "precision": "FP32 fields and stencil, FP64 bookkeeping and reductions"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "step", "bytes_per_site": BYTES_PER_SITE["f32"],
-                     "kernel_ms": kms32},
+                     "kernel": kname, "steps_per_launch": per32,
+                     "bytes_per_site_update": BYTES_PER_SITE["f32"], "kernel_ms": kms32},
     }
     if last32 is not None:
         line["last_obs"] = {"step": last32.step, "n_wind": last32.n_wind,
                             "xi_w": last32.xi_w, "v2_L": last32.v2[0]}
     if not args.no_secondary:
-        rate64, ms64, kms64, _ = run_form(AH, torch, n, AH.AH_FP64, kern, K, W)
-        print(f"# fp64 {args.kernel}: {rate64:.4g} site-updates/s", file=sys.stderr, flush=True)
-        ach64 = BYTES_PER_SITE["f64"] * n ** 3 / (kms64 * 1e-3) / 1e9
-        line["fp64"] = {"value": rate64, "ms_per_step": ms64, "kernel_ms": kms64,
-                        "achieved_GBs": ach64, "frac": ach64 / HBM_PEAK_GBS}
+        forms = [("fp32_layout%d" % other, AH.AH_FP32, kern, K, W, other, "f32"),
+                 ("fp64", AH.AH_FP64, kern, K, W, args.layout, "f64"),
+                 ("fp64_layout%d" % other, AH.AH_FP64, kern, K, W, other, "f64")]
+        for name, prec, kk, steps, warm, lay, dt in forms:
+            r_, ms_, kms_, per_, _ = run_form(AH, torch, n, prec, kk, steps, warm, lay)
+            print(f"# {name}: {r_:.4g} site-updates/s", file=sys.stderr, flush=True)
+            ach = BYTES_PER_SITE[dt] * n ** 3 * per_ / (kms_ * 1e-3) / 1e9
+            line[name] = {"value": r_, "ms_per_step": ms_, "kernel_ms": kms_,
+                          "steps_per_launch": per_, "layout": lay, "achieved_GBs": ach,
+                          "frac": ach / HBM_PEAK_GBS}
         kp = max(10, K // 4)
-        ratep, msp, kmsp, _ = run_form(AH, torch, n, AH.AH_FP64, AH.AH_KERNEL_PLAIN, kp, 2)
+        ratep, msp, kmsp, _, _ = run_form(AH, torch, n, AH.AH_FP64, AH.AH_KERNEL_PLAIN, kp, 2)
         print(f"# fp64 plain: {ratep:.4g} site-updates/s", file=sys.stderr, flush=True)
         line["plain_fp64"] = {"value": ratep, "ms_per_step": msp, "kernel_ms": kmsp,
                               "steps": kp}
         line["speedup_fp32_vs_plain_fp64"] = rate32 / ratep
-        line["speedup_fp64_vs_plain_fp64"] = rate64 / ratep
+        line["speedup_fp64_vs_plain_fp64"] = line["fp64"]["value"] / ratep
     if not args.no_secondary and not args.no_ensemble:
         rb, sb, tuning = run_ensemble(AH, torch, True, 10, True)
         rs, ss, _ = run_ensemble(AH, torch, False, 0, False)

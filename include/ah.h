@@ -27,10 +27,14 @@
  *      0 phi_re  1 phi_im  2 Pi_re  3 Pi_im  4 A_x  5 A_y  6 A_z
  *      7 E_x     8 E_y     9 E_z   10 phi_re' 11 phi_im' 12 A_x' 13 A_y' 14 A_z'
  *    Planes 10-14 are the second copy of phi and A: each step reads phi, A
- *    from one copy and writes the other.  ah_current_planes() says which
- *    copy holds the current state.  A state S_n stores phi^n, A^n and the
- *    half-step momenta Pi^{n-1/2}, E^{n-1/2}.  A_i is the raw link angle
- *    (never reduced modulo 2 pi).
+ *    from one copy and writes the other, and updates Pi, E in place.  With
+ *    layout AH_LAYOUT_20 there are 20 planes: planes 10-19 are a second copy
+ *    of all ten fields 0-9, and each pass over memory reads one copy and
+ *    writes the other (this is what lets one pass advance two steps, see
+ *    AH_KERNEL_TILED2).  ah_current_planes() says which planes hold the
+ *    current state.  A state S_n stores phi^n, A^n and the half-step momenta
+ *    Pi^{n-1/2}, E^{n-1/2}.  A_i is the raw link angle (never reduced modulo
+ *    2 pi).
  */
 #ifndef AH_H
 #define AH_H
@@ -60,9 +64,19 @@ enum {
 };
 
 enum {
-    AH_KERNEL_AUTO = 0,       /* the library's fastest variant for the shape and precision */
+    AH_KERNEL_AUTO = 0,       /* the library's fastest variant for the shape, precision and
+                                 layout (AH_KERNEL_TILED2 with AH_LAYOUT_20)                */
     AH_KERNEL_PLAIN = 1,      /* one thread per site, every neighbour read from memory     */
-    AH_KERNEL_TILED = 2       /* z-streaming tiles with LDS-staged phasors and plaquettes  */
+    AH_KERNEL_TILED = 2,      /* z-streaming tiles with LDS-staged phasors and plaquettes  */
+    AH_KERNEL_TILED2 = 3      /* two steps per pass over memory: each block advances its
+                                 tile S_n -> S_{n+2}, recomputing S_{n+1} on a one-site
+                                 ring around it; needs AH_LAYOUT_20.  Steps that measure
+                                 and an odd step left over use the AH_KERNEL_TILED pass.   */
+};
+
+enum {
+    AH_LAYOUT_15 = 0,         /* 15 planes: phi, A double-buffered, Pi, E updated in place */
+    AH_LAYOUT_20 = 1          /* 20 planes: all ten fields double-buffered                 */
 };
 
 /* Problem statement of one realization (Sec. 2 and Sec. 4 of the paper). */
@@ -79,7 +93,7 @@ typedef struct ah_params {
     double lambda0, e0, sigma; /* scalar coupling, gauge coupling, vacuum expectation   */
     uint64_t seed;        /* random-phase seed (AH_INIT_RANDOM_PHASE)                   */
     int32_t init;         /* AH_INIT_*                                                  */
-    int32_t reserved;     /* must be 0                                                  */
+    int32_t layout;       /* AH_LAYOUT_15 or AH_LAYOUT_20 (one for all realizations)    */
     int64_t step0;        /* step index n of the initial state (resume from step0)      */
     int64_t n_end;        /* 0: no limit; else the realization stops at S_{n_end} (its
                              tau_end): further steps leave it unchanged                 */
@@ -89,8 +103,8 @@ typedef struct ah_params {
                              tau_s <= 0: s throughout                                   */
 } ah_params;
 
-/* Caller-owned device memory of one realization: 15 planes, see above.
- * Alignment: 256 bytes. */
+/* Caller-owned device memory of one realization: 15 or 20 planes (per
+ * layout), see above.  Alignment: 256 bytes. */
 typedef struct ah_buffers {
     void *planes;
 } ah_buffers;
@@ -176,20 +190,24 @@ int ah_measure(ah_ctx *ctx, ah_obs *out, int8_t *wind_dev);
  */
 int ah_gauss_residual(ah_ctx *ctx, double *max_abs, double *rms);
 
-/* Plane index (0-14) of each of the 10 fields phi_re, phi_im, Pi_re, Pi_im,
- * A_x, A_y, A_z, E_x, E_y, E_z of realization r in the current state. */
+/* Plane index (0-14, or 0-19 with AH_LAYOUT_20) of each of the 10 fields
+ * phi_re, phi_im, Pi_re, Pi_im, A_x, A_y, A_z, E_x, E_y, E_z of realization r
+ * in the current state. */
 int ah_current_planes(const ah_ctx *ctx, int32_t r, int32_t plane_of_field[10]);
 
 /* Step index n of the current state of realization r. */
 int ah_current_step(const ah_ctx *ctx, int32_t r, int64_t *n);
 
 /*
- * Select the step-kernel variant (AH_KERNEL_*) and, for AH_KERNEL_TILED, the
- * tile: tile_y rows of 64 sites per block (2, 4, 8, or 16 for FP32) and
- * chunk_z planes per block along z (>= 1).  0 picks the library default.  AH_KERNEL_TILED
- * needs nx % 64 == 0 in every realization (AH_E_INVALID otherwise).  Results do not
- * depend on the choice beyond floating-point rounding of the same formulas;
- * the tiled variants of one precision agree bit for bit.
+ * Select the step-kernel variant (AH_KERNEL_*) and, for the tiled kernels, the
+ * tile: tile_y rows of 64 sites per block and chunk_z planes per block along
+ * z (>= 1); 0 picks the library default.  tile_y: AH_KERNEL_TILED 2, 4, 8, or
+ * 16 for FP32; AH_KERNEL_TILED2 4 or 8 for FP32, 4 for FP64 (its measuring
+ * and odd steps keep the AH_KERNEL_TILED defaults).  The tiled kernels need
+ * nx % 64 == 0 in every realization, AH_KERNEL_TILED2 also AH_LAYOUT_20
+ * (AH_E_INVALID otherwise).  Results do not depend on the choice beyond
+ * floating-point rounding of the same formulas; the tiled variants of one
+ * precision, AH_KERNEL_TILED2 included, agree bit for bit.
  */
 int ah_set_kernel(ah_ctx *ctx, int32_t kernel, int32_t tile_y, int32_t chunk_z);
 
@@ -208,9 +226,10 @@ int ah_set_kernel(ah_ctx *ctx, int32_t kernel, int32_t tile_y, int32_t chunk_z);
 int ah_set_launch(ah_ctx *ctx, int32_t batched, int32_t graph_steps);
 
 /*
- * Autotuner: times the tiled step kernel for candidate tile heights and
- * z-chunks on a scratch lattice of each distinct shape of the context (the
- * caller's fields are not touched; scratch of up to 15 planes of
+ * Autotuner: times the tiled step kernel (AH_KERNEL_TILED2 when that is the
+ * selected or automatic choice, else AH_KERNEL_TILED) for candidate tile
+ * heights and z-chunks on a scratch lattice of each distinct shape of the
+ * context (the caller's fields are not touched; scratch of up to 20 planes of
  * nx*ny*min(nz,128) is allocated and freed), installs the tile height with
  * the least estimated total time per step and the best z-chunk for each
  * realization, and returns them in *tile_y and chunk_z[n_real] (either may be

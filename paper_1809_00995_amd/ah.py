@@ -1,6 +1,6 @@
 """ctypes binding of ``libah.so`` (include/ah.h), argument marshalling only.
 
-PyTorch supplies device memory (one tensor of 15 planes per realization) and
+PyTorch supplies device memory (one tensor of 15 or 20 planes per realization) and
 the stream; every step of the method runs in the library's HIP kernels.  If
 the library has not been built this module raises on load: there is no CPU
 fallback.
@@ -20,7 +20,8 @@ AH_OK, AH_E_INVALID, AH_E_NOMEM, AH_E_HIP, AH_E_DOMAIN, AH_E_STATE, AH_E_NONFINI
     0, -1, -2, -3, -4, -5, -6
 AH_FP64, AH_FP32 = 0, 1
 AH_INIT_RANDOM_PHASE, AH_INIT_VACUUM, AH_INIT_NONE = 0, 1, 2
-AH_KERNEL_AUTO, AH_KERNEL_PLAIN, AH_KERNEL_TILED = 0, 1, 2
+AH_KERNEL_AUTO, AH_KERNEL_PLAIN, AH_KERNEL_TILED, AH_KERNEL_TILED2 = 0, 1, 2, 3
+AH_LAYOUT_15, AH_LAYOUT_20 = 0, 1
 
 FIELDS = ("phi_re", "phi_im", "pi_re", "pi_im", "ax", "ay", "az", "ex", "ey", "ez")
 EXPORTED = ("ah_error_string", "ah_last_error", "ah_init", "ah_step", "ah_measure",
@@ -41,7 +42,7 @@ class _Params(C.Structure):
                 ("tau0", C.c_double), ("tau_ref", C.c_double),
                 ("era_p", C.c_double), ("s", C.c_double),
                 ("lambda0", C.c_double), ("e0", C.c_double), ("sigma", C.c_double),
-                ("seed", C.c_uint64), ("init", C.c_int32), ("reserved", C.c_int32),
+                ("seed", C.c_uint64), ("init", C.c_int32), ("layout", C.c_int32),
                 ("step0", C.c_int64), ("n_end", C.c_int64),
                 ("s_late", C.c_double), ("tau_s", C.c_double)]
 
@@ -119,12 +120,17 @@ class Params:
     n_end: int = 0
     s_late: float = 1.0
     tau_s: float = 0.0
+    layout: int = AH_LAYOUT_15
 
     def _c(self) -> _Params:
         return _Params(self.nx, self.ny, self.nz, self.precision, self.dx, self.dt, self.tau0,
                        self.tau_ref, self.era_p, self.s, self.lambda0, self.e0, self.sigma,
-                       self.seed & 0xFFFFFFFFFFFFFFFF, self.init, 0, self.step0, self.n_end,
-                       self.s_late, self.tau_s)
+                       self.seed & 0xFFFFFFFFFFFFFFFF, self.init, self.layout, self.step0,
+                       self.n_end, self.s_late, self.tau_s)
+
+    @property
+    def planes(self) -> int:
+        return 20 if self.layout == AH_LAYOUT_20 else 15
 
     @property
     def dtype(self):
@@ -173,8 +179,9 @@ class Obs:
 
 
 def alloc_planes(p: Params, device="cuda") -> torch.Tensor:
-    """Caller-owned field storage: 15 planes (see include/ah.h), shape (15, nz, ny, nx)."""
-    return torch.empty((15, p.nz, p.ny, p.nx), dtype=p.dtype, device=device)
+    """Caller-owned field storage: 15 or 20 planes by layout (see include/ah.h), shape
+    (planes, nz, ny, nx)."""
+    return torch.empty((p.planes, p.nz, p.ny, p.nx), dtype=p.dtype, device=device)
 
 
 def _check(lib, ctx, rc):
@@ -195,9 +202,10 @@ class Context:
             raise ValueError("one planes tensor per realization is required")
         for p, t in zip(self.params, self.planes):
             if (not t.is_cuda or t.dtype != p.dtype or not t.is_contiguous()
-                    or t.numel() != 15 * p.sites):
-                raise ValueError("planes must be contiguous device tensors of 15*nx*ny*nz "
-                                 "elements of the realization's precision")
+                    or t.numel() != p.planes * p.sites):
+                raise ValueError("planes must be contiguous device tensors of 15 (or 20 with "
+                                 "AH_LAYOUT_20) planes of nx*ny*nz elements of the "
+                                 "realization's precision")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         n = len(self.params)
         cp = (_Params * n)(*[p._c() for p in self.params])

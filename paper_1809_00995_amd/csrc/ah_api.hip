@@ -19,18 +19,22 @@
 #include "k_measure.hpp"
 #include "k_step_plain.hpp"
 #include "k_step_tiled.hpp"
+#include "k_step_tiled2.hpp"
 
 using namespace ah;
 
 struct ah_ctx {
     int nreal = 0;
     int prec = AH_FP64;
+    int layout = AH_LAYOUT_15;
     hipStream_t stream = nullptr;
     std::vector<ah_params> p;
     std::vector<int64_t> step;        // host mirror of each realization's step index
+    std::vector<int32_t> copy;        // host mirror of the copy holding its state
     RealDesc *d_desc = nullptr;
     int64_t *d_step = nullptr;
-    Coef *d_coef = nullptr;
+    int32_t *d_copy = nullptr;
+    Coef *d_coef = nullptr;           // [2][nreal]: steps n and n+1 of a pass
     Slot *d_slots = nullptr;          // measurement slots
     ah_obs *d_obs = nullptr;
     int64_t slot_cap = 0;             // slots allocated, in states (x nreal)
@@ -39,6 +43,8 @@ struct ah_ctx {
     int kernel = AH_KERNEL_AUTO;
     int tile_y = 0;                   // 0: default
     std::vector<int> cz;              // per-realization z-chunk, 0: default
+    int tile_y2 = 0;                  // the same for the two-step kernel
+    std::vector<int> cz2;
     int batched = 0;                  // 1: one persistent launch per step
     int graph_steps = 0;              // > 0: replay runs of unmeasured steps from a graph
     // batched work list (rebuilt when the configuration changes)
@@ -96,7 +102,7 @@ double scale_factor_host(const ah_params &p, double tau) {
     return std::pow(t / p.tau_ref, p.era_p);
 }
 
-int validate(const ah_params &q, int r, const ah_buffers &b, int prec) {
+int validate(const ah_params &q, int r, const ah_buffers &b, int prec, int layout) {
     auto bad = [&](int code, const char *what) {
         return fail(nullptr, code, "realization %d: %s", r, what);
     };
@@ -125,8 +131,12 @@ int validate(const ah_params &q, int r, const ah_buffers &b, int prec) {
         return bad(AH_E_DOMAIN, "tau_ref must be > 0 and tau0 finite");
     if (!(q.lambda0 >= 0.0) || !(q.e0 > 0.0) || !(q.sigma > 0.0))
         return bad(AH_E_DOMAIN, "need lambda0 >= 0, e0 > 0, sigma > 0");
-    if (q.init < AH_INIT_RANDOM_PHASE || q.init > AH_INIT_NONE || q.reserved != 0)
-        return bad(AH_E_INVALID, "bad init kind or reserved field");
+    if (q.init < AH_INIT_RANDOM_PHASE || q.init > AH_INIT_NONE)
+        return bad(AH_E_INVALID, "bad init kind");
+    if (q.layout != AH_LAYOUT_15 && q.layout != AH_LAYOUT_20)
+        return bad(AH_E_INVALID, "layout must be AH_LAYOUT_15 or AH_LAYOUT_20");
+    if (q.layout != layout)
+        return bad(AH_E_INVALID, "all realizations must share one layout");
     if (q.n_end < 0 || (q.n_end > 0 && q.n_end < q.step0))
         return bad(AH_E_INVALID, "n_end must be 0 or >= step0");
     double tau_half = q.tau0 + ((double)q.step0 + 0.5) * q.dt;
@@ -176,9 +186,11 @@ int launch_zero(ah_ctx *c, void *p, size_t bytes) {
     return AH_OK;
 }
 
-int launch_bookkeep(ah_ctx *c, int advance) {
+// steps = 0: coefficients of the current state; 1 or 2: of the next pass
+// (one or two steps), advancing the device counters.
+int launch_bookkeep(ah_ctx *c, int steps) {
     hipLaunchKernelGGL(k_bookkeep, dim3((c->nreal + 63) / 64), dim3(64), 0, c->stream, c->d_desc,
-                       c->d_step, c->d_coef, c->nreal, advance);
+                       c->d_step, c->d_copy, c->d_coef, c->nreal, steps);
     HIP_TRY(c, hipGetLastError());
     return AH_OK;
 }
@@ -191,11 +203,20 @@ bool tiled_ok(const ah_ctx *c) {
 }
 
 bool use_tiled(const ah_ctx *c, int r) {
-    return c->kernel == AH_KERNEL_TILED || (c->kernel == AH_KERNEL_AUTO && c->p[r].nx % 64 == 0);
+    return c->kernel == AH_KERNEL_TILED || c->kernel == AH_KERNEL_TILED2 ||
+           (c->kernel == AH_KERNEL_AUTO && c->p[r].nx % 64 == 0);
+}
+
+// Unmeasured steps go in pairs through the two-step kernel: explicitly, or by
+// default in the 20-plane layout (per-realization launches only).
+bool use_tiled2(const ah_ctx *c) {
+    if (c->layout != AH_LAYOUT_20 || !tiled_ok(c))
+        return false;
+    return c->kernel == AH_KERNEL_TILED2 || c->kernel == AH_KERNEL_AUTO;
 }
 
 // The batched kernel needs tiled shapes and one common step index (so every
-// realization measures at the same steps).
+// realization measures at the same steps).  It advances one step per launch.
 bool batch_ok(const ah_ctx *c) {
     if (!c->batched || c->kernel == AH_KERNEL_PLAIN || !tiled_ok(c))
         return false;
@@ -308,13 +329,29 @@ int build_items(ah_ctx *c) {
     return AH_OK;
 }
 
-// One step of every realization: bookkeeping, then the batched kernel or one
-// launch per realization.  slots_row[r] receives the measurement of
-// realization r when want_meas[r] (slots_row == NULL: no measurement).  With
-// skip_frozen the host leaves out realizations that reached n_end (the device
-// skips them anyway, which keeps captured graphs valid).
-int launch_one_step(ah_ctx *c, Slot *slots_row, const char *want_meas, bool skip_frozen) {
-    TRY(launch_bookkeep(c, 1));
+// One pass over memory of every realization: bookkeeping for `steps` (1 or
+// 2) steps, then the kernels.  A one-step pass uses the batched kernel or one
+// launch per realization; slots_row[r] receives the measurement of
+// realization r when want_meas[r] (slots_row == NULL: no measurement).  A
+// two-step pass (never measuring) launches the two-step kernel per
+// realization.  With skip_frozen the host leaves out realizations that
+// reached n_end (the device skips them anyway, which keeps captured graphs
+// valid).
+int launch_pass(ah_ctx *c, int steps, Slot *slots_row, const char *want_meas, bool skip_frozen) {
+    TRY(launch_bookkeep(c, steps));
+    if (steps == 2) {
+        for (int r = 0; r < c->nreal; ++r) {
+            if (skip_frozen && frozen(c, r))
+                continue;
+            const ah_params &q = c->p[r];
+            int rc = launch_step_tiled2(c->prec == AH_FP64, c->d_desc, c->d_coef, r, c->nreal, q.nx,
+                                        q.ny, q.nz, c->tile_y2, c->cz2[r], c->stream);
+            if (rc)
+                return fail(c, AH_E_HIP, "two-step kernel launch failed: %s",
+                            hipGetErrorString((hipError_t)rc));
+        }
+        return AH_OK;
+    }
     if (batch_ok(c)) {
         TRY(build_items(c));
         const int mode = slots_row ? MODE_STEP_MEASURE : MODE_STEP;
@@ -335,12 +372,29 @@ int launch_one_step(ah_ctx *c, Slot *slots_row, const char *want_meas, bool skip
     return AH_OK;
 }
 
-void advance_mirror(ah_ctx *c, int64_t k) {
+// Host mirror of k_bookkeep for one pass of `steps` steps.
+void mirror_pass(ah_ctx *c, int steps) {
     for (int r = 0; r < c->nreal; ++r) {
-        const ah_params &q = c->p[r];
-        int64_t n = c->step[r] + k;
-        c->step[r] = (q.n_end > 0 && n > q.n_end) ? std::max(c->step[r], q.n_end) : n;
+        if (frozen(c, r))
+            continue;
+        c->step[r] += 1;
+        c->copy[r] ^= 1;
+        if (steps == 2 && !frozen(c, r))
+            c->step[r] += 1;
     }
+}
+
+// Passes that advance g steps: pairs through the two-step kernel where it is
+// in use (and the launch is not batched), then a single step for an odd one.
+std::vector<int> pass_plan(const ah_ctx *c, int64_t g) {
+    std::vector<int> v;
+    const bool two = use_tiled2(c) && !batch_ok(c);
+    for (int64_t k = 0; k < g;) {
+        const int s = two && g - k >= 2 ? 2 : 1;
+        v.push_back(s);
+        k += s;
+    }
+    return v;
 }
 
 // Capture graph_steps unmeasured steps once (on the context's own stream)
@@ -354,13 +408,14 @@ int run_graph(ah_ctx *c, int64_t reps) {
     }
     if (batch_ok(c))
         TRY(build_items(c));     // outside the capture: it copies and synchronises
+    const std::vector<int> plan = pass_plan(c, c->graph_steps);
     if (!c->gexec_valid) {
         hipStream_t user = c->stream;
         HIP_TRY(c, hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
         c->stream = c->gstream;
         int rc = AH_OK;
-        for (int k = 0; k < c->graph_steps && rc == AH_OK; ++k)
-            rc = launch_one_step(c, nullptr, nullptr, false);
+        for (size_t k = 0; k < plan.size() && rc == AH_OK; ++k)
+            rc = launch_pass(c, plan[k], nullptr, nullptr, false);
         c->stream = user;
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(c->gstream, &graph);
@@ -383,7 +438,9 @@ int run_graph(ah_ctx *c, int64_t reps) {
         HIP_TRY(c, hipGraphLaunch(c->gexec, c->gstream));
     HIP_TRY(c, hipEventRecord(c->ev_out, c->gstream));
     HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_out, 0));
-    advance_mirror(c, reps * c->graph_steps);
+    for (int64_t k = 0; k < reps; ++k)
+        for (int s : plan)
+            mirror_pass(c, s);
     return AH_OK;
 }
 
@@ -398,7 +455,8 @@ void release(ah_ctx *c) {
         (void)hipEventDestroy(c->ev_out);
     if (c->gstream)
         (void)hipStreamDestroy(c->gstream);
-    void *ptrs[] = { c->d_desc, c->d_step, c->d_coef, c->d_slots, c->d_obs, c->d_gauss, c->d_items };
+    void *ptrs[] = { c->d_desc, c->d_step, c->d_copy, c->d_coef, c->d_slots, c->d_obs, c->d_gauss,
+                     c->d_items };
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -435,17 +493,20 @@ int ah_init(ah_ctx **out, int32_t n_real, const ah_params *p, const ah_buffers *
     if (n_real < 1 || !p || !buf)
         return fail(nullptr, AH_E_INVALID, "need n_real >= 1 and non-NULL params and buffers");
     for (int r = 0; r < n_real; ++r)
-        TRY(validate(p[r], r, buf[r], p[0].precision));
+        TRY(validate(p[r], r, buf[r], p[0].precision, p[0].layout));
 
     ah_ctx *c = new (std::nothrow) ah_ctx;
     if (!c)
         return fail(nullptr, AH_E_NOMEM, "host allocation failed");
     c->nreal = n_real;
     c->prec = p[0].precision;
+    c->layout = p[0].layout;
     c->stream = (hipStream_t)hip_stream;
     c->p.assign(p, p + n_real);
     c->step.resize(n_real);
+    c->copy.assign(n_real, 0);
     c->cz.assign(n_real, 0);
+    c->cz2.assign(n_real, 0);
 
     std::vector<RealDesc> desc(n_real);
     for (int r = 0; r < n_real; ++r) {
@@ -456,6 +517,8 @@ int ah_init(ah_ctx **out, int32_t n_real, const ah_params *p, const ah_buffers *
         d.ny = q.ny;
         d.nz = q.nz;
         d.elem = c->prec == AH_FP64 ? 8 : 4;
+        d.layout = q.layout;
+        d.pad = 0;
         d.N = sites_of(q);
         d.dx = q.dx;
         d.dt = q.dt;
@@ -483,7 +546,9 @@ int ah_init(ah_ctx **out, int32_t n_real, const ah_params *p, const ah_buffers *
         return hip_fail(e, "hipMalloc(desc)");
     if ((e = hipMalloc(&c->d_step, n_real * sizeof(int64_t))) != hipSuccess)
         return hip_fail(e, "hipMalloc(step)");
-    if ((e = hipMalloc(&c->d_coef, n_real * sizeof(Coef))) != hipSuccess)
+    if ((e = hipMalloc(&c->d_copy, n_real * sizeof(int32_t))) != hipSuccess)
+        return hip_fail(e, "hipMalloc(copy)");
+    if ((e = hipMalloc(&c->d_coef, 2 * n_real * sizeof(Coef))) != hipSuccess)
         return hip_fail(e, "hipMalloc(coef)");
     if ((e = hipMalloc(&c->d_gauss, n_real * 2 * sizeof(unsigned long long))) != hipSuccess)
         return hip_fail(e, "hipMalloc(gauss)");
@@ -493,6 +558,9 @@ int ah_init(ah_ctx **out, int32_t n_real, const ah_params *p, const ah_buffers *
     if ((e = hipMemcpyAsync(c->d_step, c->step.data(), n_real * sizeof(int64_t),
                             hipMemcpyHostToDevice, c->stream)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(step)");
+    if ((e = hipMemcpyAsync(c->d_copy, c->copy.data(), n_real * sizeof(int32_t),
+                            hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(copy)");
     for (int r = 0; r < n_real; ++r) {
         if (p[r].init == AH_INIT_NONE)
             continue;
@@ -558,10 +626,11 @@ int ah_step(ah_ctx *c, int64_t nsteps, int32_t measure_every, ah_obs *out, int64
 
     size_t next = 0;
     int64_t i = 0;
+    const bool two = use_tiled2(c) && !batch_ok(c);
     while (i < nsteps) {
         if (next < meas.size() && meas_at[next] == i) {
-            TRY(launch_one_step(c, c->d_slots + next * c->nreal, meas[next].data(), true));
-            advance_mirror(c, 1);
+            TRY(launch_pass(c, 1, c->d_slots + next * c->nreal, meas[next].data(), true));
+            mirror_pass(c, 1);
             ++next;
             ++i;
             continue;
@@ -573,9 +642,10 @@ int ah_step(ah_ctx *c, int64_t nsteps, int32_t measure_every, ah_obs *out, int64
             i += reps * c->graph_steps;
             continue;
         }
-        TRY(launch_one_step(c, nullptr, nullptr, true));
-        advance_mirror(c, 1);
-        ++i;
+        const int s = two && stop - i >= 2 ? 2 : 1;
+        TRY(launch_pass(c, s, nullptr, nullptr, true));
+        mirror_pass(c, s);
+        i += s;
     }
 
     if (measure_every > 0) {
@@ -657,9 +727,8 @@ int ah_gauss_residual(ah_ctx *c, double *max_abs, double *rms) {
 int ah_current_planes(const ah_ctx *c, int32_t r, int32_t plane_of_field[10]) {
     if (!c || !plane_of_field || r < 0 || r >= c->nreal)
         return AH_E_INVALID;
-    const int par = (int)((c->step[r] - c->p[r].step0) & 1);
     for (int f = 0; f < 10; ++f)
-        plane_of_field[f] = field_plane(f, par);
+        plane_of_field[f] = field_plane(f, c->copy[r], c->layout);
     return AH_OK;
 }
 
@@ -674,15 +743,27 @@ int ah_set_kernel(ah_ctx *c, int32_t kernel, int32_t tile_y, int32_t chunk_z) {
     if (!c)
         return fail(nullptr, AH_E_INVALID, "NULL context");
     c->err.clear();
-    if (kernel < AH_KERNEL_AUTO || kernel > AH_KERNEL_TILED)
+    if (kernel < AH_KERNEL_AUTO || kernel > AH_KERNEL_TILED2)
         return fail(c, AH_E_INVALID, "unknown kernel %d", kernel);
-    if (chunk_z < 0 || (tile_y != 0 && !tiled_ty_valid(c->prec == AH_FP64, tile_y)))
-        return fail(c, AH_E_INVALID, "tile_y must be 0, 2, 4, 8 (or 16 for FP32); chunk_z >= 0");
-    if (kernel == AH_KERNEL_TILED && !tiled_ok(c))
+    const bool fp64 = c->prec == AH_FP64;
+    if (chunk_z < 0)
+        return fail(c, AH_E_INVALID, "chunk_z must be >= 0");
+    if (kernel == AH_KERNEL_TILED2) {
+        if (tile_y != 0 && !tiled2_ty_valid(fp64, tile_y))
+            return fail(c, AH_E_INVALID, "two-step kernel: tile_y must be 0, 4 (or 8 for FP32)");
+        if (c->layout != AH_LAYOUT_20)
+            return fail(c, AH_E_INVALID, "two-step kernel needs AH_LAYOUT_20");
+    } else if (tile_y != 0 && !tiled_ty_valid(fp64, tile_y)) {
+        return fail(c, AH_E_INVALID, "tile_y must be 0, 2, 4, 8 (or 16 for FP32)");
+    }
+    if ((kernel == AH_KERNEL_TILED || kernel == AH_KERNEL_TILED2) && !tiled_ok(c))
         return fail(c, AH_E_INVALID, "tiled kernel needs nx %% 64 == 0");
     c->kernel = kernel;
-    c->tile_y = tile_y;
-    c->cz.assign(c->nreal, chunk_z);
+    const bool two = kernel == AH_KERNEL_TILED2;
+    c->tile_y = two ? 0 : tile_y;
+    c->cz.assign(c->nreal, two ? 0 : chunk_z);
+    c->tile_y2 = two ? tile_y : 0;
+    c->cz2.assign(c->nreal, two ? chunk_z : 0);
     invalidate_plans(c);
     return AH_OK;
 }
@@ -706,10 +787,12 @@ int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
     if (c->kernel == AH_KERNEL_PLAIN || !tiled_ok(c))
         return fail(c, AH_E_STATE, "autotuning needs the tiled kernel (nx %% 64 == 0)");
     const bool fp64 = c->prec == AH_FP64;
+    // the kernel that runs the unmeasured steps
+    const bool two = use_tiled2(c) && !batch_ok(c);
     const int ty_cap = c->batched ? tiled_ty_max(fp64, MODE_STEP_MEASURE) : tiled_ty_max(fp64, MODE_STEP);
     std::vector<int> tys;
     for (int t : { 4, 8, 16 })
-        if (tiled_ty_valid(fp64, t) && t <= ty_cap)
+        if (two ? tiled2_ty_valid(fp64, t) : (tiled_ty_valid(fp64, t) && t <= ty_cap))
             tys.push_back(t);
 
     // distinct shapes; each is timed on a scratch lattice of its own, so the
@@ -737,6 +820,7 @@ int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
     RealDesc *d_desc = nullptr;
     Coef *d_coef = nullptr;
     int64_t *d_step = nullptr;
+    int32_t *d_copy = nullptr;
     char *scratch = nullptr;
     int rc = AH_OK;
     auto hip_ok = [&](hipError_t e, const char *what) {
@@ -746,13 +830,15 @@ int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
     };
     if (hip_ok(hipEventCreate(&e0), "hipEventCreate") && hip_ok(hipEventCreate(&e1), "hipEventCreate") &&
         hip_ok(hipMalloc(&d_desc, sizeof(RealDesc)), "hipMalloc") &&
-        hip_ok(hipMalloc(&d_coef, sizeof(Coef)), "hipMalloc") &&
-        hip_ok(hipMalloc(&d_step, sizeof(int64_t)), "hipMalloc")) {
+        hip_ok(hipMalloc(&d_coef, 2 * sizeof(Coef)), "hipMalloc") &&
+        hip_ok(hipMalloc(&d_step, sizeof(int64_t)), "hipMalloc") &&
+        hip_ok(hipMalloc(&d_copy, sizeof(int32_t)), "hipMalloc")) {
         for (Shape &sh : shapes) {
             // time a slab of at most 128 planes: the cost per plane is what is tuned
             const int nzs = std::min(sh.nz, 128);
             const int64_t N = (int64_t)sh.nx * sh.ny * nzs;
-            const size_t bytes = (size_t)N * 15 * (fp64 ? 8 : 4);
+            const int layout = two ? AH_LAYOUT_20 : AH_LAYOUT_15;
+            const size_t bytes = (size_t)N * plane_count(layout) * (fp64 ? 8 : 4);
             if (!hip_ok(hipMalloc(&scratch, bytes), "hipMalloc(scratch)"))
                 break;
             const ah_params &q0 = c->p[0];
@@ -762,6 +848,7 @@ int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
             d.ny = sh.ny;
             d.nz = nzs;
             d.elem = fp64 ? 8 : 4;
+            d.layout = layout;
             d.N = N;
             d.dx = q0.dx;
             d.dt = q0.dt;
@@ -773,8 +860,10 @@ int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
             d.e0 = q0.e0;
             d.sigma = q0.sigma;
             const int64_t s0 = 0;
+            const int32_t cp0 = 0;
             hip_ok(hipMemcpyAsync(d_desc, &d, sizeof d, hipMemcpyHostToDevice, c->stream), "copy");
             hip_ok(hipMemcpyAsync(d_step, &s0, sizeof s0, hipMemcpyHostToDevice, c->stream), "copy");
+            hip_ok(hipMemcpyAsync(d_copy, &cp0, sizeof cp0, hipMemcpyHostToDevice, c->stream), "copy");
             dim3 ig(grid_for(N, 256, 8192));
             if (fp64)
                 hipLaunchKernelGGL(k_init<double>, ig, dim3(256), 0, c->stream, d_desc, 0,
@@ -782,8 +871,9 @@ int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
             else
                 hipLaunchKernelGGL(k_init<float>, ig, dim3(256), 0, c->stream, d_desc, 0,
                                    (int)AH_INIT_RANDOM_PHASE, (uint64_t)12345);
-            hipLaunchKernelGGL(k_bookkeep, dim3(1), dim3(64), 0, c->stream, d_desc, d_step, d_coef,
-                               1, 0);
+            // coefficients of steps 0 and 1, read from copy 0 by every timed launch
+            hipLaunchKernelGGL(k_bookkeep, dim3(1), dim3(64), 0, c->stream, d_desc, d_step, d_copy,
+                               d_coef, 1, two ? 2 : 0);
             hip_ok(hipGetLastError(), "launch");
             for (int t : tys) {
                 double best = 1e300;
@@ -794,16 +884,20 @@ int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
                     for (int k = 0; k < 4 && rc == AH_OK; ++k) {
                         if (k == 1)
                             hip_ok(hipEventRecord(e0, c->stream), "hipEventRecord");
-                        hip_ok((hipError_t)launch_step_tiled(fp64, MODE_STEP, d_desc, d_coef, 0,
-                                                             sh.nx, sh.ny, nzs, t, z, nullptr,
-                                                             nullptr, c->stream),
+                        hip_ok((hipError_t)(two ? launch_step_tiled2(fp64, d_desc, d_coef, 0, 1,
+                                                                     sh.nx, sh.ny, nzs, t, z,
+                                                                     c->stream)
+                                                 : launch_step_tiled(fp64, MODE_STEP, d_desc, d_coef,
+                                                                     0, sh.nx, sh.ny, nzs, t, z,
+                                                                     nullptr, nullptr, c->stream)),
                                "tiled launch");
                     }
                     float ms = 0.f;
                     hip_ok(hipEventRecord(e1, c->stream), "hipEventRecord");
                     hip_ok(hipEventSynchronize(e1), "hipEventSynchronize");
                     hip_ok(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-                    const double per_plane = ms / 3.0 / nzs;
+                    // per plane and step
+                    const double per_plane = ms / 3.0 / nzs / (two ? 2.0 : 1.0);
                     if (per_plane < best) {
                         best = per_plane;
                         best_cz = z;
@@ -828,6 +922,8 @@ int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
         (void)hipFree(d_coef);
     if (d_step)
         (void)hipFree(d_step);
+    if (d_copy)
+        (void)hipFree(d_copy);
     if (e0)
         (void)hipEventDestroy(e0);
     if (e1)
@@ -847,15 +943,17 @@ int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
             bi = (int)i;
         }
     }
-    c->tile_y = tys[bi];
+    int &ty_set = two ? c->tile_y2 : c->tile_y;
+    std::vector<int> &cz_set = two ? c->cz2 : c->cz;
+    ty_set = tys[bi];
     for (int r = 0; r < c->nreal; ++r)
-        c->cz[r] = shapes[shape_of[r]].cz[bi];
+        cz_set[r] = shapes[shape_of[r]].cz[bi];
     invalidate_plans(c);
     if (tile_y)
-        *tile_y = c->tile_y;
+        *tile_y = ty_set;
     if (chunk_z)
         for (int r = 0; r < c->nreal; ++r)
-            chunk_z[r] = c->cz[r];
+            chunk_z[r] = cz_set[r];
     return AH_OK;
 }
 

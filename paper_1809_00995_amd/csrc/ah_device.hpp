@@ -15,15 +15,18 @@ namespace ah {
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr double kTwoPi = 6.28318530717958647692528676655900577;
 
-// Plane numbers of the caller's 15-plane buffer.
+// Field numbers (planes of the first copy) and the second-copy planes of
+// phi and A in the 15-plane layout.
 enum : int { P_PHR = 0, P_PHI = 1, P_PIR = 2, P_PII = 3, P_AX = 4, P_EX = 7,
              P_PHR2 = 10, P_AX2 = 12 };
 
 // Static description of one realization (written once by ah_init).
 struct RealDesc {
-    char *base;            // 15 planes of N elements
+    char *base;            // 15 or 20 planes of N elements
     int32_t nx, ny, nz;
     int32_t elem;          // bytes per element (4 or 8)
+    int32_t layout;        // AH_LAYOUT_15 or AH_LAYOUT_20
+    int32_t pad;
     int64_t N;             // nx * ny * nz
     double dx, dt, tau0, tau_ref, era_p, s, lambda0, e0, sigma;
     int64_t step0, n_end;
@@ -35,7 +38,7 @@ struct RealDesc {
 struct Coef {
     int64_t n;             // step index of the state being read
     int32_t active;        // 0 once the realization has reached n_end
-    int32_t parity;        // 0: phi, A in planes 0,1,4-6; 1: in planes 10-14
+    int32_t parity;        // copy holding the state read (see field_plane)
     double tau, a_m, a_0, a_p;
     double s_m, s_0;       // comoving-width parameter at tau_{n-1/2}, tau_n
     double c1, c2, c3;     // Pi update, Eq. (4)
@@ -66,15 +69,23 @@ template <typename T> __device__ __forceinline__ T* plane(const RealDesc &d, int
     return reinterpret_cast<T*>(d.base + (size_t)k * (size_t)d.N * sizeof(T));
 }
 
-// Current-state plane of field f (0..9) for the given ping-pong parity.
-__host__ __device__ __forceinline__ int field_plane(int f, int parity) {
+// Plane of field f (0..9) in copy `parity` (0 or 1).  AH_LAYOUT_15: copy 1
+// of phi and A is planes 10-14 and Pi, E have one plane each (updated in
+// place); AH_LAYOUT_20: copy 1 of every field is plane f + 10.
+__host__ __device__ __forceinline__ int field_plane(int f, int parity, int layout) {
     if (!parity)
         return f;
+    if (layout == AH_LAYOUT_20)
+        return f + 10;
     if (f < 2)
         return P_PHR2 + f;
     if (f >= 4 && f < 7)
         return P_AX2 + (f - 4);
     return f;
+}
+
+__host__ __device__ __forceinline__ int plane_count(int layout) {
+    return layout == AH_LAYOUT_20 ? 20 : 15;
 }
 
 __device__ __forceinline__ void sincos_t(float x, float *s, float *c) { sincosf(x, s, c); }

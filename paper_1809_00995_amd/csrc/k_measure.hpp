@@ -37,7 +37,7 @@ k_measure_plain(const RealDesc *descs, const Coef *coefs, int r, Slot *slot, int
     const int par = c.parity;
     const T *F[10];
     for (int f = 0; f < 10; ++f)
-        F[f] = plane<T>(d, field_plane(f, par));
+        F[f] = plane<T>(d, field_plane(f, par, d.layout));
     const double a = c.a_0, a2 = a * a;
     const double g = pow(a, 2.0 * (1.0 - c.s_0)) / (2.0 * d.e0 * d.e0);
     const double h = d.lambda0 * pow(a, 2.0 + 2.0 * c.s_0);
@@ -166,9 +166,11 @@ k_gauss(const RealDesc *descs, const Coef *coefs, int r, unsigned long long *out
     const Coef c = coefs[r];
     const int nx = d.nx, ny = d.ny, nz = d.nz;
     const int par = c.parity;
-    const T *phr = plane<T>(d, field_plane(0, par)), *phi = plane<T>(d, field_plane(1, par));
-    const T *pir = plane<T>(d, P_PIR), *pii = plane<T>(d, P_PII);
-    const T *E[3] = { plane<T>(d, P_EX), plane<T>(d, P_EX + 1), plane<T>(d, P_EX + 2) };
+    const int L = d.layout;
+    const T *phr = plane<T>(d, field_plane(0, par, L)), *phi = plane<T>(d, field_plane(1, par, L));
+    const T *pir = plane<T>(d, field_plane(2, par, L)), *pii = plane<T>(d, field_plane(3, par, L));
+    const T *E[3] = { plane<T>(d, field_plane(7, par, L)), plane<T>(d, field_plane(8, par, L)),
+                      plane<T>(d, field_plane(9, par, L)) };
     const double fe = pow(c.a_m, 2.0 * (1.0 - c.s_m)) / (d.e0 * d.e0);
     const double fp = 2.0 * d.dx * d.dx * c.a_m * c.a_m;
     double mx = 0.0, sq = 0.0;

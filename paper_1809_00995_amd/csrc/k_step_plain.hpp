@@ -27,8 +27,9 @@ __device__ __forceinline__ int site_shift(int x, int y, int z, int sx, int sy, i
 //          - d2 sum_{j != i} [sin Xi_ij^x - sin Xi_ij^{x-j}],
 //   Xi_ij^y = A_i^y + A_j^{y+i} - A_i^{y+j} - A_j^y                (Eq. (3))
 //   phi^{n+1} = phi^n + dt Pi+,  A^{n+1} = A^n + dt E+.
-// Pi and E are updated in place (each is read only at its own site); phi and
-// A are read from one copy and written to the other.
+// phi and A are read from one copy and written to the other; Pi and E are
+// updated in place in the 15-plane layout (each is read only at its own
+// site) and written to the other copy in the 20-plane layout.
 template <typename T>
 __global__ void __launch_bounds__(256) k_step_plain(const RealDesc *descs, const Coef *coefs, int r) {
     const RealDesc d = descs[r];
@@ -43,16 +44,21 @@ __global__ void __launch_bounds__(256) k_step_plain(const RealDesc *descs, const
     const int x = o % nx, y = (o / nx) % ny, z = o / (nx * ny);
     const int par = c.parity;
 
-    const T *phr = plane<T>(d, field_plane(0, par));
-    const T *phi = plane<T>(d, field_plane(1, par));
-    const T *A[3] = { plane<T>(d, field_plane(4, par)), plane<T>(d, field_plane(5, par)),
-                      plane<T>(d, field_plane(6, par)) };
-    T *pir = plane<T>(d, P_PIR), *pii = plane<T>(d, P_PII);
-    T *E[3] = { plane<T>(d, P_EX), plane<T>(d, P_EX + 1), plane<T>(d, P_EX + 2) };
-    T *phr_o = plane<T>(d, field_plane(0, par ^ 1));
-    T *phi_o = plane<T>(d, field_plane(1, par ^ 1));
-    T *A_o[3] = { plane<T>(d, field_plane(4, par ^ 1)), plane<T>(d, field_plane(5, par ^ 1)),
-                  plane<T>(d, field_plane(6, par ^ 1)) };
+    const int L = d.layout;
+    const T *phr = plane<T>(d, field_plane(0, par, L));
+    const T *phi = plane<T>(d, field_plane(1, par, L));
+    const T *A[3] = { plane<T>(d, field_plane(4, par, L)), plane<T>(d, field_plane(5, par, L)),
+                      plane<T>(d, field_plane(6, par, L)) };
+    const T *pir = plane<T>(d, field_plane(2, par, L)), *pii = plane<T>(d, field_plane(3, par, L));
+    const T *E[3] = { plane<T>(d, field_plane(7, par, L)), plane<T>(d, field_plane(8, par, L)),
+                      plane<T>(d, field_plane(9, par, L)) };
+    T *pir_o = plane<T>(d, field_plane(2, par ^ 1, L)), *pii_o = plane<T>(d, field_plane(3, par ^ 1, L));
+    T *E_o[3] = { plane<T>(d, field_plane(7, par ^ 1, L)), plane<T>(d, field_plane(8, par ^ 1, L)),
+                  plane<T>(d, field_plane(9, par ^ 1, L)) };
+    T *phr_o = plane<T>(d, field_plane(0, par ^ 1, L));
+    T *phi_o = plane<T>(d, field_plane(1, par ^ 1, L));
+    T *A_o[3] = { plane<T>(d, field_plane(4, par ^ 1, L)), plane<T>(d, field_plane(5, par ^ 1, L)),
+                  plane<T>(d, field_plane(6, par ^ 1, L)) };
 
     const T c1 = (T)c.c1, c2 = (T)c.c2, c3 = (T)c.c3;
     const T d1 = (T)c.d1, d2 = (T)c.d2, d3 = (T)c.d3;
@@ -86,8 +92,8 @@ __global__ void __launch_bounds__(256) k_step_plain(const RealDesc *descs, const
     const T v = pr * pr + pm * pm - s2;
     const T pnr = c1 * pir[o] + c2 * lr - c3 * v * pr;
     const T pni = c1 * pii[o] + c2 * li - c3 * v * pm;
-    pir[o] = pnr;
-    pii[o] = pni;
+    pir_o[o] = pnr;
+    pii_o[o] = pni;
     phr_o[o] = pr + dt * pnr;    // Eq. (6)
     phi_o[o] = pm + dt * pni;
 
@@ -108,7 +114,7 @@ __global__ void __launch_bounds__(256) k_step_plain(const RealDesc *descs, const
             curl += sin_t(xi0) - sin_t(xi1);
         }
         const T en = d1 * E[i][o] + d3 * cur - d2 * curl;
-        E[i][o] = en;
+        E_o[i][o] = en;
         A_o[i][o] = a[i] + dt * en;             // Eq. (7)
     }
 }

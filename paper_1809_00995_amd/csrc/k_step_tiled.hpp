@@ -93,6 +93,84 @@ template <typename T> struct SiteV {
     double th;
 };
 
+// Everything the update of one site x reads (Eqs. (4)-(7)), gathered by the
+// kernel: phi, A and the link phasors U_i = e^{iA_i} at x, the momenta at x,
+// phi at the six neighbours, the backward links U_j(x-j), and the sines of
+// the nine plaquettes that contain a link of x (Eq. (3)).  Suffixes name the
+// site: _xp is x+x, _ym is x-y, and so on.
+template <typename T> struct Stencil {
+    T pr, pm, ax, ay, az, uxc, uxs, uyc, uys, uzc, uzs;
+    T pr0, pi0, ex0, ey0, ez0;
+    T pr_xp, pi_xp, pr_xm, pi_xm, pr_yp, pi_yp, pr_ym, pi_ym, pr_zp, pi_zp, pr_zm, pi_zm;
+    T uxc_xm, uxs_xm, uyc_ym, uys_ym, uzc_zm, uzs_zm;
+    T pxy, pxy_xm, pxy_ym, pyz, pyz_ym, pyz_zm, pzx, pzx_xm, pzx_zm;
+};
+
+// New values of the site: Pi^{n+1/2}, E^{n+1/2}, phi^{n+1}, A^{n+1}.
+template <typename T> struct SiteNew {
+    T pr, pi, ex, ey, ez, qr, qi, ax, ay, az;
+};
+
+// Step coefficients of Eqs. (4)-(5) in the stencil's precision.
+template <typename T> struct StepK {
+    T c1, c2, c3, d1, d2, d3, dt, s2;
+};
+
+template <typename T> __device__ __forceinline__ StepK<T> step_k(const RealDesc &d, const Coef &c) {
+    return StepK<T>{ (T)c.c1, (T)c.c2, (T)c.c3, (T)c.d1, (T)c.d2, (T)c.d3, (T)d.dt,
+                     (T)(d.sigma * d.sigma) };
+}
+
+// The leapfrog update of one site, Eqs. (4)-(7).  Contraction is off and
+// every fused multiply-add is written out, so the rounding is the same in
+// every kernel that calls it: the tiled kernels of any tile shape, and the
+// two-steps-per-pass kernel, agree bit for bit.
+template <typename T>
+__device__ __forceinline__ SiteNew<T> leapfrog_site(const Stencil<T> &s, const StepK<T> &k) {
+#pragma clang fp contract(off)
+    // Eq. (4): sum_j [U_j(x) phi(x+j) + conj(U_j(x-j)) phi(x-j)] - 6 phi(x)
+    T lr = (T)-6 * s.pr, li = (T)-6 * s.pm;
+    lr = fma(s.uxc, s.pr_xp, lr);    lr = fma(-s.uxs, s.pi_xp, lr);
+    li = fma(s.uxc, s.pi_xp, li);    li = fma(s.uxs, s.pr_xp, li);
+    lr = fma(s.uxc_xm, s.pr_xm, lr); lr = fma(s.uxs_xm, s.pi_xm, lr);
+    li = fma(s.uxc_xm, s.pi_xm, li); li = fma(-s.uxs_xm, s.pr_xm, li);
+    lr = fma(s.uyc, s.pr_yp, lr);    lr = fma(-s.uys, s.pi_yp, lr);
+    li = fma(s.uyc, s.pi_yp, li);    li = fma(s.uys, s.pr_yp, li);
+    lr = fma(s.uyc_ym, s.pr_ym, lr); lr = fma(s.uys_ym, s.pi_ym, lr);
+    li = fma(s.uyc_ym, s.pi_ym, li); li = fma(-s.uys_ym, s.pr_ym, li);
+    lr = fma(s.uzc, s.pr_zp, lr);    lr = fma(-s.uzs, s.pi_zp, lr);
+    li = fma(s.uzc, s.pi_zp, li);    li = fma(s.uzs, s.pr_zp, li);
+    lr = fma(s.uzc_zm, s.pr_zm, lr); lr = fma(s.uzs_zm, s.pi_zm, lr);
+    li = fma(s.uzc_zm, s.pi_zm, li); li = fma(-s.uzs_zm, s.pr_zm, li);
+    const T v = fma(s.pr, s.pr, s.pm * s.pm) - k.s2;
+    const T cv = k.c3 * v;
+    SiteNew<T> o;
+    o.pr = fma(k.c1, s.pr0, fma(k.c2, lr, -(cv * s.pr)));
+    o.pi = fma(k.c1, s.pi0, fma(k.c2, li, -(cv * s.pm)));
+
+    // Eq. (5): current Im[conj(phi(x+i)) conj(U_i(x)) phi(x)] and the lattice curl
+    const T wxr = fma(s.uxc, s.pr, s.uxs * s.pm), wxi = fma(s.uxc, s.pm, -(s.uxs * s.pr));
+    const T wyr = fma(s.uyc, s.pr, s.uys * s.pm), wyi = fma(s.uyc, s.pm, -(s.uys * s.pr));
+    const T wzr = fma(s.uzc, s.pr, s.uzs * s.pm), wzi = fma(s.uzc, s.pm, -(s.uzs * s.pr));
+    const T jx = fma(s.pr_xp, wxi, -(s.pi_xp * wxr));
+    const T jy = fma(s.pr_yp, wyi, -(s.pi_yp * wyr));
+    const T jz = fma(s.pr_zp, wzi, -(s.pi_zp * wzr));
+    const T curl_x = (s.pxy - s.pxy_ym) - (s.pzx - s.pzx_zm);
+    const T curl_y = (s.pyz - s.pyz_zm) - (s.pxy - s.pxy_xm);
+    const T curl_z = (s.pzx - s.pzx_xm) - (s.pyz - s.pyz_ym);
+    o.ex = fma(k.d1, s.ex0, fma(k.d3, jx, -(k.d2 * curl_x)));
+    o.ey = fma(k.d1, s.ey0, fma(k.d3, jy, -(k.d2 * curl_y)));
+    o.ez = fma(k.d1, s.ez0, fma(k.d3, jz, -(k.d2 * curl_z)));
+
+    // Eqs. (6)-(7)
+    o.qr = fma(k.dt, o.pr, s.pr);
+    o.qi = fma(k.dt, o.pi, s.pm);
+    o.ax = fma(k.dt, o.ex, s.ax);
+    o.ay = fma(k.dt, o.ey, s.ay);
+    o.az = fma(k.dt, o.ez, s.az);
+    return o;
+}
+
 __device__ __forceinline__ int wrap_mod(int v, int n) {
     v %= n;
     return v < 0 ? v + n : v;
@@ -133,23 +211,23 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
     const int gy = wrap_mod(y0 + ly, ny);
     const int q = G::li(lx, ly);
 
-    const int par = c.parity;
-    const T *phr = plane<T>(d, field_plane(0, par));
-    const T *phi = plane<T>(d, field_plane(1, par));
-    const T *A0 = plane<T>(d, field_plane(4, par));
-    const T *A1 = plane<T>(d, field_plane(5, par));
-    const T *A2 = plane<T>(d, field_plane(6, par));
-    T *pir = plane<T>(d, P_PIR), *pii = plane<T>(d, P_PII);
-    T *E0 = plane<T>(d, P_EX), *E1 = plane<T>(d, P_EX + 1), *E2 = plane<T>(d, P_EX + 2);
-    T *ophr = plane<T>(d, field_plane(0, par ^ 1));
-    T *ophi = plane<T>(d, field_plane(1, par ^ 1));
-    T *oA0 = plane<T>(d, field_plane(4, par ^ 1));
-    T *oA1 = plane<T>(d, field_plane(5, par ^ 1));
-    T *oA2 = plane<T>(d, field_plane(6, par ^ 1));
+    const int par = c.parity, L = d.layout;
+    const T *phr = plane<T>(d, field_plane(0, par, L));
+    const T *phi = plane<T>(d, field_plane(1, par, L));
+    const T *A0 = plane<T>(d, field_plane(4, par, L));
+    const T *A1 = plane<T>(d, field_plane(5, par, L));
+    const T *A2 = plane<T>(d, field_plane(6, par, L));
+    const T *pir = plane<T>(d, field_plane(2, par, L)), *pii = plane<T>(d, field_plane(3, par, L));
+    const T *E0 = plane<T>(d, field_plane(7, par, L)), *E1 = plane<T>(d, field_plane(8, par, L));
+    const T *E2 = plane<T>(d, field_plane(9, par, L));
+    // the new state: phi, A always to the other copy; Pi, E in place in the
+    // 15-plane layout (each thread reads them only at its own site)
+    T *o[10];
+    for (int f = 0; f < 10; ++f)
+        o[f] = plane<T>(d, field_plane(f, par ^ 1, L));
 
-    const T c1 = (T)c.c1, c2 = (T)c.c2, c3 = (T)c.c3;
-    const T d1 = (T)c.d1, d2 = (T)c.d2, d3 = (T)c.d3;
-    const T dt = (T)d.dt, s2 = (T)(d.sigma * d.sigma);
+    const StepK<T> K = step_k<T>(d, c);
+    const T s2 = K.s2;
 
     // measurement constants and per-thread FP64 accumulators
     double msum[A_COUNT];
@@ -271,44 +349,32 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
 
         const T pr = cur.pr, pm = cur.pm;
         if (UPD) {
-            // Eq. (4): sum_j [U_j(x) phi(x+j) + conj(U_j(x-j)) phi(x-j)] - 6 phi
-            T lr = (T)-6 * pr, lim = (T)-6 * pm;
-            lr += cur.uxc * pr_xp - cur.uxs * pi_xp + uxc_xm * pr_xm + uxs_xm * pi_xm;
-            lim += cur.uxc * pi_xp + cur.uxs * pr_xp + uxc_xm * pi_xm - uxs_xm * pr_xm;
-            lr += cur.uyc * pr_yp - cur.uys * pi_yp + uyc_ym * pr_ym + uys_ym * pi_ym;
-            lim += cur.uyc * pi_yp + cur.uys * pr_yp + uyc_ym * pi_ym - uys_ym * pr_ym;
-            lr += cur.uzc * nxt.pr - cur.uzs * nxt.pm + uzc_m * phr_m + uzs_m * phi_m;
-            lim += cur.uzc * nxt.pm + cur.uzs * nxt.pr + uzc_m * phi_m - uzs_m * phr_m;
-            const T v = pr * pr + pm * pm - s2;
-            const T pnr = c1 * pr0 + c2 * lr - c3 * v * pr;
-            const T pni = c1 * pi0 + c2 * lim - c3 * v * pm;
-
-            // Eq. (5): current Im[conj(phi(x+i)) conj(U_i) phi(x)] and the curl
-            const T wxr = cur.uxc * pr + cur.uxs * pm, wxi = cur.uxc * pm - cur.uxs * pr;
-            const T wyr = cur.uyc * pr + cur.uys * pm, wyi = cur.uyc * pm - cur.uys * pr;
-            const T wzr = cur.uzc * pr + cur.uzs * pm, wzi = cur.uzc * pm - cur.uzs * pr;
-            const T jx = pr_xp * wxi - pi_xp * wxr;
-            const T jy = pr_yp * wyi - pi_yp * wyr;
-            const T jz = nxt.pr * wzi - nxt.pm * wzr;
-            const T curl_x = (pxy - pxy_ym) - (pzx - pzx_m);
-            const T curl_y = (pyz - pyz_m) - (pxy - pxy_xm);
-            const T curl_z = (pzx - pzx_xm) - (pyz - pyz_ym);
-            const T enx = d1 * ex0 + d3 * jx - d2 * curl_x;
-            const T eny = d1 * ey0 + d3 * jy - d2 * curl_y;
-            const T enz = d1 * ez0 + d3 * jz - d2 * curl_z;
-
+            Stencil<T> st;
+            st.pr = pr; st.pm = pm; st.ax = cur.ax; st.ay = cur.ay; st.az = cur.az;
+            st.uxc = cur.uxc; st.uxs = cur.uxs; st.uyc = cur.uyc; st.uys = cur.uys;
+            st.uzc = cur.uzc; st.uzs = cur.uzs;
+            st.pr0 = pr0; st.pi0 = pi0; st.ex0 = ex0; st.ey0 = ey0; st.ez0 = ez0;
+            st.pr_xp = pr_xp; st.pi_xp = pi_xp; st.pr_xm = pr_xm; st.pi_xm = pi_xm;
+            st.pr_yp = pr_yp; st.pi_yp = pi_yp; st.pr_ym = pr_ym; st.pi_ym = pi_ym;
+            st.pr_zp = nxt.pr; st.pi_zp = nxt.pm; st.pr_zm = phr_m; st.pi_zm = phi_m;
+            st.uxc_xm = uxc_xm; st.uxs_xm = uxs_xm; st.uyc_ym = uyc_ym; st.uys_ym = uys_ym;
+            st.uzc_zm = uzc_m; st.uzs_zm = uzs_m;
+            st.pxy = pxy; st.pxy_xm = pxy_xm; st.pxy_ym = pxy_ym;
+            st.pyz = pyz; st.pyz_ym = pyz_ym; st.pyz_zm = pyz_m;
+            st.pzx = pzx; st.pzx_xm = pzx_xm; st.pzx_zm = pzx_m;
+            const SiteNew<T> nw = leapfrog_site(st, K);
             if (owner) {
                 // streaming stores: the new state is not read again in this launch
-                __builtin_nontemporal_store(pnr, pir + s);
-                __builtin_nontemporal_store(pni, pii + s);
-                __builtin_nontemporal_store(enx, E0 + s);
-                __builtin_nontemporal_store(eny, E1 + s);
-                __builtin_nontemporal_store(enz, E2 + s);
-                __builtin_nontemporal_store((T)(pr + dt * pnr), ophr + s);        // Eq. (6)
-                __builtin_nontemporal_store((T)(pm + dt * pni), ophi + s);
-                __builtin_nontemporal_store((T)(cur.ax + dt * enx), oA0 + s);    // Eq. (7)
-                __builtin_nontemporal_store((T)(cur.ay + dt * eny), oA1 + s);
-                __builtin_nontemporal_store((T)(cur.az + dt * enz), oA2 + s);
+                __builtin_nontemporal_store(nw.pr, o[2] + s);
+                __builtin_nontemporal_store(nw.pi, o[3] + s);
+                __builtin_nontemporal_store(nw.ex, o[7] + s);
+                __builtin_nontemporal_store(nw.ey, o[8] + s);
+                __builtin_nontemporal_store(nw.ez, o[9] + s);
+                __builtin_nontemporal_store(nw.qr, o[0] + s);
+                __builtin_nontemporal_store(nw.qi, o[1] + s);
+                __builtin_nontemporal_store(nw.ax, o[4] + s);
+                __builtin_nontemporal_store(nw.ay, o[5] + s);
+                __builtin_nontemporal_store(nw.az, o[6] + s);
             }
         }
 

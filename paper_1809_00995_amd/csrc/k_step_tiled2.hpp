@@ -1,0 +1,452 @@
+// k_step_tiled2.hpp -- two leapfrog steps per pass over memory (temporal
+// blocking) in the 20-plane layout.
+//
+// A single-step pass reads and writes the whole state once per step, and at
+// 512^3 that runs at the speed of a device copy.  Here each block advances
+// its 64 x TY tile from S_n to S_{n+2} while reading S_n and writing S_{n+2}
+// once: the intermediate state S_{n+1} lives in LDS only.
+//
+// Geometry, per z-plane (R1 = tile + one-site ring, R2 = R1 + one more ring):
+//  - S_n (phi and the link phasors) is staged in LDS on R2: the tile's own
+//    sites and the R1 ring come from the threads that update them (in
+//    registers), the outer ring from the ring wavefronts.
+//  - Step one (Eqs. (4)-(7) with the coefficients of step n) is computed on
+//    all of R1: TY wavefronts hold the tile's rows (64 sites each, as in the
+//    single-step kernel) and NRW ring wavefronts hold the R1 ring.  S_{n+1}'s
+//    phi and phasors go to LDS.
+//  - Step two (coefficients of step n+1) is computed on the tile, one plane
+//    behind step one, and S_{n+2} is written to the other copy.
+// The ring costs (66 (TY+2)) / (64 TY) extra site updates of step one.  The
+// momenta Pi, E of S_n are read by neighbouring blocks (their R1 ring) while
+// this block writes S_{n+2}: that is why every field has two copies.
+//
+// Both steps use leapfrog_site and plaq_sin, so S_{n+2} is bitwise what two
+// single-step tiled passes give.  When the second step of the pair is not
+// active (the realization reaches n_end after one step), the kernel writes
+// S_{n+1} instead.
+#pragma once
+
+#include "k_step_tiled.hpp"
+
+namespace ah {
+
+template <int TY> struct Tile2Geom {
+    static constexpr int W1 = 66, H1 = TY + 2, S1 = W1 * H1;   // R1
+    static constexpr int W2 = 68, H2 = TY + 4, S2 = W2 * H2;   // R2
+    static constexpr int RING1 = 2 * W1 + 2 * TY;              // R1 minus the tile
+    static constexpr int RING2 = 2 * W2 + 2 * H1;              // R2 minus R1
+    static constexpr int NRW = (RING1 + 63) / 64;              // ring wavefronts
+    static constexpr int NW = TY + NRW;                        // wavefronts per block
+    static_assert(RING2 <= 64 * NRW, "the ring wavefronts stage the outer ring");
+    static_assert(NW <= 16, "at most 1024 threads per block");
+    static __device__ __forceinline__ int i1(int lx, int ly) { return (ly + 1) * W1 + (lx + 1); }
+    static __device__ __forceinline__ int i2(int lx, int ly) { return (ly + 2) * W2 + (lx + 2); }
+    // h-th site of the R1 ring: rows -1 and TY (x = -1..64), then columns -1 and 64 (y = 0..TY-1)
+    static __device__ __forceinline__ void ring1(int h, int &lx, int &ly) {
+        if (h < W1) {
+            lx = h - 1;
+            ly = -1;
+        } else if (h < 2 * W1) {
+            lx = h - W1 - 1;
+            ly = TY;
+        } else if (h < 2 * W1 + TY) {
+            lx = -1;
+            ly = h - 2 * W1;
+        } else {
+            lx = 64;
+            ly = h - 2 * W1 - TY;
+        }
+    }
+    // h-th site of the R2 ring: rows -2 and TY+1 (x = -2..65), then columns -2 and 65 (y = -1..TY)
+    static __device__ __forceinline__ void ring2(int h, int &lx, int &ly) {
+        if (h < W2) {
+            lx = h - 2;
+            ly = -2;
+        } else if (h < 2 * W2) {
+            lx = h - W2 - 2;
+            ly = TY + 1;
+        } else if (h < 2 * W2 + H1) {
+            lx = -2;
+            ly = h - 2 * W2 - 1;
+        } else {
+            lx = 65;
+            ly = h - 2 * W2 - H1 - 1;
+        }
+    }
+};
+
+// phi and the three link phasors of one site (the LDS record of a state).
+template <typename T> struct Phasors {
+    T pr, pm, uxc, uxs, uyc, uys, uzc, uzs;
+};
+
+// A site's own values carried from plane z-1 to plane z: phi, U_z, and the yz
+// and zx plaquettes based at the site.
+template <typename T> struct Below {
+    T pr, pm, uzc, uzs, pyz, pzx;
+};
+
+// Gather the stencil of the site at LDS index q of a state staged with row
+// width W: buffer C holds plane z, buffer N plane z+1.  own/up are the site's
+// values at z and z+1 (registers), bel its carried values from z-1, and
+// pi_e its momenta at z.
+template <typename T, int W, int S>
+__device__ __forceinline__ Stencil<T> gather(const T (*C)[S], const T (*N)[S], int q,
+                                             const Phasors<T> &own, T ax, T ay, T az,
+                                             const Phasors<T> &up, const Below<T> &bel,
+                                             T pr0, T pi0, T ex0, T ey0, T ez0,
+                                             T &pyz_out, T &pzx_out) {
+    Stencil<T> st;
+    st.pr = own.pr; st.pm = own.pm; st.ax = ax; st.ay = ay; st.az = az;
+    st.uxc = own.uxc; st.uxs = own.uxs; st.uyc = own.uyc; st.uys = own.uys;
+    st.uzc = own.uzc; st.uzs = own.uzs;
+    st.pr0 = pr0; st.pi0 = pi0; st.ex0 = ex0; st.ey0 = ey0; st.ez0 = ez0;
+    st.pr_xp = C[Q_PR][q + 1]; st.pi_xp = C[Q_PI][q + 1];
+    st.pr_xm = C[Q_PR][q - 1]; st.pi_xm = C[Q_PI][q - 1];
+    st.pr_yp = C[Q_PR][q + W]; st.pi_yp = C[Q_PI][q + W];
+    st.pr_ym = C[Q_PR][q - W]; st.pi_ym = C[Q_PI][q - W];
+    st.pr_zp = up.pr; st.pi_zp = up.pm; st.pr_zm = bel.pr; st.pi_zm = bel.pm;
+    const T uxc_xm = C[Q_UXC][q - 1], uxs_xm = C[Q_UXS][q - 1];
+    const T uxc_yp = C[Q_UXC][q + W], uxs_yp = C[Q_UXS][q + W];
+    const T uxc_xmyp = C[Q_UXC][q - 1 + W], uxs_xmyp = C[Q_UXS][q - 1 + W];
+    const T uxc_ym = C[Q_UXC][q - W], uxs_ym = C[Q_UXS][q - W];
+    const T uyc_xp = C[Q_UYC][q + 1], uys_xp = C[Q_UYS][q + 1];
+    const T uyc_ym = C[Q_UYC][q - W], uys_ym = C[Q_UYS][q - W];
+    const T uyc_xm = C[Q_UYC][q - 1], uys_xm = C[Q_UYS][q - 1];
+    const T uyc_xpym = C[Q_UYC][q + 1 - W], uys_xpym = C[Q_UYS][q + 1 - W];
+    const T uzc_xp = C[Q_UZC][q + 1], uzs_xp = C[Q_UZS][q + 1];
+    const T uzc_yp = C[Q_UZC][q + W], uzs_yp = C[Q_UZS][q + W];
+    const T uzc_xm = C[Q_UZC][q - 1], uzs_xm = C[Q_UZS][q - 1];
+    const T uzc_ym = C[Q_UZC][q - W], uzs_ym = C[Q_UZS][q - W];
+    const T uxc_xmzp = N[Q_UXC][q - 1], uxs_xmzp = N[Q_UXS][q - 1];
+    const T uyc_ymzp = N[Q_UYC][q - W], uys_ymzp = N[Q_UYS][q - W];
+    st.uxc_xm = uxc_xm; st.uxs_xm = uxs_xm; st.uyc_ym = uyc_ym; st.uys_ym = uys_ym;
+    st.uzc_zm = bel.uzc; st.uzs_zm = bel.uzs;
+    // plaquette sines (Eq. (3)), same argument order as the single-step kernel
+    st.pxy = plaq_sin(own.uxc, own.uxs, uyc_xp, uys_xp, uxc_yp, uxs_yp, own.uyc, own.uys);
+    st.pxy_xm = plaq_sin(uxc_xm, uxs_xm, own.uyc, own.uys, uxc_xmyp, uxs_xmyp, uyc_xm, uys_xm);
+    st.pxy_ym = plaq_sin(uxc_ym, uxs_ym, uyc_xpym, uys_xpym, own.uxc, own.uxs, uyc_ym, uys_ym);
+    st.pyz = plaq_sin(own.uyc, own.uys, uzc_yp, uzs_yp, up.uyc, up.uys, own.uzc, own.uzs);
+    st.pyz_ym = plaq_sin(uyc_ym, uys_ym, own.uzc, own.uzs, uyc_ymzp, uys_ymzp, uzc_ym, uzs_ym);
+    st.pzx = plaq_sin(own.uzc, own.uzs, up.uxc, up.uxs, uzc_xp, uzs_xp, own.uxc, own.uxs);
+    st.pzx_xm = plaq_sin(uzc_xm, uzs_xm, uxc_xmzp, uxs_xmzp, own.uzc, own.uzs, uxc_xm, uxs_xm);
+    st.pyz_zm = bel.pyz;
+    st.pzx_zm = bel.pzx;
+    pyz_out = st.pyz;
+    pzx_out = st.pzx;
+    return st;
+}
+
+// The yz and zx plaquettes based at the site of LDS index q on plane z
+// (buffer C), with own/up its values at z and z+1: the carried values of the
+// first plane of a chunk.
+template <typename T, int W, int S>
+__device__ __forceinline__ void base_plaquettes(const T (*C)[S], int q, const Phasors<T> &own,
+                                                const Phasors<T> &up, T &pyz, T &pzx) {
+    pyz = plaq_sin(own.uyc, own.uys, C[Q_UZC][q + W], C[Q_UZS][q + W], up.uyc, up.uys, own.uzc,
+                   own.uzs);
+    pzx = plaq_sin(own.uzc, own.uzs, up.uxc, up.uxs, C[Q_UZC][q + 1], C[Q_UZS][q + 1], own.uxc,
+                   own.uxs);
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void put_phasors(T (*B)[S], int k, const Phasors<T> &v) {
+    B[Q_PR][k] = v.pr;
+    B[Q_PI][k] = v.pm;
+    B[Q_UXC][k] = v.uxc;
+    B[Q_UXS][k] = v.uxs;
+    B[Q_UYC][k] = v.uyc;
+    B[Q_UYS][k] = v.uys;
+    B[Q_UZC][k] = v.uzc;
+    B[Q_UZS][k] = v.uzs;
+}
+
+template <typename T>
+__device__ __forceinline__ Phasors<T> make_phasors(T pr, T pm, T ax, T ay, T az) {
+    Phasors<T> v;
+    v.pr = pr;
+    v.pm = pm;
+    sincos_t(ax, &v.uxs, &v.uxc);
+    sincos_t(ay, &v.uys, &v.uyc);
+    sincos_t(az, &v.uzs, &v.uzc);
+    return v;
+}
+
+// One tile (64 x TY sites, planes [z0, z0 + cz)) of one realization: S_n in
+// copy c0.parity -> S_{n+2} (or S_{n+1} when c1 is not active) in the other
+// copy.  Every thread of the block calls it with the same arguments.
+template <typename T, int TY>
+__device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, const Coef &c1,
+                                            int tile, int cz) {
+    using G = Tile2Geom<TY>;
+    __shared__ T sa[2][Q_COUNT][G::S2];   // S_n on R2, planes z and z+1
+    __shared__ T sb[2][Q_COUNT][G::S1];   // S_{n+1} on R1, two planes
+
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    const int ntx = nx >> 6, nty = (ny + TY - 1) / TY;
+    const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+    const int x0 = tx << 6, y0 = ty * TY, z0 = tz * cz;
+    const int z1 = min(z0 + cz, nz);
+    const bool two = c1.active != 0;
+
+    const int t = threadIdx.x;
+    const bool inner = t < 64 * TY;            // wave-uniform
+    int lx, ly;
+    bool has1 = true;
+    if (inner) {
+        lx = t & 63;
+        ly = t >> 6;
+    } else {
+        const int h = t - 64 * TY;
+        has1 = h < G::RING1;
+        G::ring1(has1 ? h : 0, lx, ly);
+    }
+    const bool owner = inner && (y0 + ly) < ny;
+    const int gx = wrap_mod(x0 + lx, nx), gy = wrap_mod(y0 + ly, ny);
+    const int q2 = G::i2(lx, ly), q1 = G::i1(lx, ly);
+    // outer-ring staging by the ring wavefronts
+    int h2 = inner ? G::RING2 : t - 64 * TY;
+    int rx = 0, ry = 0;
+    const bool stager = h2 < G::RING2;
+    if (stager)
+        G::ring2(h2, rx, ry);
+    const int rq = G::i2(rx, ry);
+    const int rgx = wrap_mod(x0 + rx, nx), rgy = wrap_mod(y0 + ry, ny);
+
+    const int par = c0.parity, L = d.layout;
+    const T *in[10];
+    T *out[10];
+    for (int f = 0; f < 10; ++f) {
+        in[f] = plane<T>(d, field_plane(f, par, L));
+        out[f] = plane<T>(d, field_plane(f, par ^ 1, L));
+    }
+    const StepK<T> K0 = step_k<T>(d, c0), K1 = step_k<T>(d, c1);
+
+    auto own_site = [&](int z) { return gx + nx * (gy + ny * z); };
+    auto zwrap = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
+    // S_n at (own site, z): phi, A and phasors
+    struct Raw {
+        T pr, pm, ax, ay, az;
+    };
+    auto load_raw = [&](int s) {
+        Raw r;
+        r.pr = in[0][s];
+        r.pm = in[1][s];
+        r.ax = in[4][s];
+        r.ay = in[5][s];
+        r.az = in[6][s];
+        return r;
+    };
+    auto stage_ring = [&](int bf, int z) {
+        if (stager) {
+            const Raw r = load_raw(rgx + nx * (rgy + ny * z));
+            put_phasors<T, G::S2>(sa[bf], rq, make_phasors(r.pr, r.pm, r.ax, r.ay, r.az));
+        }
+    };
+
+    // ---- prologue: S_n planes z0-2 (buffer 1) and z0-1 (buffer 0)
+    const int za = zwrap(z0 - 2), zb = zwrap(z0 - 1);
+    Raw rcur, rnxt;
+    Phasors<T> pcur, pnxt;
+    Below<T> bel;
+    {
+        const Raw rb = load_raw(own_site(za));
+        const Phasors<T> pb = make_phasors(rb.pr, rb.pm, rb.ax, rb.ay, rb.az);
+        if (has1)
+            put_phasors<T, G::S2>(sa[1], q2, pb);
+        stage_ring(1, za);
+        rcur = load_raw(own_site(zb));
+        pcur = make_phasors(rcur.pr, rcur.pm, rcur.ax, rcur.ay, rcur.az);
+        if (has1)
+            put_phasors<T, G::S2>(sa[0], q2, pcur);
+        stage_ring(0, zb);
+        __syncthreads();
+        bel.pyz = bel.pzx = 0;
+        if (has1)
+            base_plaquettes<T, G::W2, G::S2>(sa[1], q2, pb, pcur, bel.pyz, bel.pzx);
+        bel.pr = pb.pr;
+        bel.pm = pb.pm;
+        bel.uzc = pb.uzc;
+        bel.uzs = pb.uzs;
+        __syncthreads();
+    }
+
+    // S_{n+1} at the own site: cur1 (plane p), the carried values below it
+    Phasors<T> pc1;
+    T c1ax = 0, c1ay = 0, c1az = 0, c1pr = 0, c1pi = 0, c1ex = 0, c1ey = 0, c1ez = 0;
+    Below<T> bel1;
+    bel1.pr = bel1.pm = bel1.uzc = bel1.uzs = bel1.pyz = bel1.pzx = 0;
+    pc1.pr = pc1.pm = pc1.uxc = pc1.uxs = pc1.uyc = pc1.uys = pc1.uzc = pc1.uzs = 0;
+
+    const int nk = (z1 - z0) + 2;
+    for (int k = 0; k < nk; ++k) {
+        const int zs = zwrap(z0 - 1 + k);          // plane of step one
+        const int zn = zwrap(z0 + k);              // plane zs + 1
+        const int cb = k & 1, nb = cb ^ 1;
+        const int s = own_site(zs);
+        // (a) stage S_n at zs+1; read the momenta of S_n at zs
+        T pr0 = 0, pi0 = 0, ex0 = 0, ey0 = 0, ez0 = 0;
+        if (has1) {
+            pr0 = in[2][s];
+            pi0 = in[3][s];
+            ex0 = in[7][s];
+            ey0 = in[8][s];
+            ez0 = in[9][s];
+            rnxt = load_raw(own_site(zn));
+            pnxt = make_phasors(rnxt.pr, rnxt.pm, rnxt.ax, rnxt.ay, rnxt.az);
+            put_phasors<T, G::S2>(sa[nb], q2, pnxt);
+        }
+        stage_ring(nb, zn);
+        __syncthreads();
+
+        // (b) step one at (own R1 site, zs)
+        SiteNew<T> n1{};
+        Phasors<T> pn1{};
+        if (has1) {
+            T pyz, pzx;
+            const Stencil<T> st = gather<T, G::W2, G::S2>(sa[cb], sa[nb], q2, pcur, rcur.ax, rcur.ay,
+                                                          rcur.az, pnxt, bel, pr0, pi0, ex0, ey0,
+                                                          ez0, pyz, pzx);
+            n1 = leapfrog_site(st, K0);
+            bel.pr = pcur.pr;
+            bel.pm = pcur.pm;
+            bel.uzc = pcur.uzc;
+            bel.uzs = pcur.uzs;
+            bel.pyz = pyz;
+            bel.pzx = pzx;
+            rcur = rnxt;
+            pcur = pnxt;
+            if (two) {
+                pn1 = make_phasors(n1.qr, n1.qi, n1.ax, n1.ay, n1.az);
+                put_phasors<T, G::S1>(sb[cb], q1, pn1);
+            }
+        }
+        if (!two) {
+            // one step only: the tile's S_{n+1} is final
+            if (owner && k >= 1 && k <= z1 - z0) {
+                __builtin_nontemporal_store(n1.pr, out[2] + s);
+                __builtin_nontemporal_store(n1.pi, out[3] + s);
+                __builtin_nontemporal_store(n1.ex, out[7] + s);
+                __builtin_nontemporal_store(n1.ey, out[8] + s);
+                __builtin_nontemporal_store(n1.ez, out[9] + s);
+                __builtin_nontemporal_store(n1.qr, out[0] + s);
+                __builtin_nontemporal_store(n1.qi, out[1] + s);
+                __builtin_nontemporal_store(n1.ax, out[4] + s);
+                __builtin_nontemporal_store(n1.ay, out[5] + s);
+                __builtin_nontemporal_store(n1.az, out[6] + s);
+            }
+            __syncthreads();
+            continue;
+        }
+        __syncthreads();
+
+        // (c) step two at (tile site, p = zs - 1), one plane behind
+        if (inner) {
+            if (k == 1) {
+                // carried values of plane z0-1 for the first plane of step two
+                base_plaquettes<T, G::W1, G::S1>(sb[0], q1, pc1, pn1, bel1.pyz, bel1.pzx);
+                bel1.pr = pc1.pr;
+                bel1.pm = pc1.pm;
+                bel1.uzc = pc1.uzc;
+                bel1.uzs = pc1.uzs;
+            } else if (k >= 2) {
+                T pyz, pzx;
+                const Stencil<T> st = gather<T, G::W1, G::S1>(sb[nb], sb[cb], q1, pc1, c1ax, c1ay,
+                                                              c1az, pn1, bel1, c1pr, c1pi, c1ex,
+                                                              c1ey, c1ez, pyz, pzx);
+                const SiteNew<T> n2 = leapfrog_site(st, K1);
+                if (owner) {
+                    const int sp = own_site(zwrap(zs - 1));
+                    __builtin_nontemporal_store(n2.pr, out[2] + sp);
+                    __builtin_nontemporal_store(n2.pi, out[3] + sp);
+                    __builtin_nontemporal_store(n2.ex, out[7] + sp);
+                    __builtin_nontemporal_store(n2.ey, out[8] + sp);
+                    __builtin_nontemporal_store(n2.ez, out[9] + sp);
+                    __builtin_nontemporal_store(n2.qr, out[0] + sp);
+                    __builtin_nontemporal_store(n2.qi, out[1] + sp);
+                    __builtin_nontemporal_store(n2.ax, out[4] + sp);
+                    __builtin_nontemporal_store(n2.ay, out[5] + sp);
+                    __builtin_nontemporal_store(n2.az, out[6] + sp);
+                }
+                bel1.pr = pc1.pr;
+                bel1.pm = pc1.pm;
+                bel1.uzc = pc1.uzc;
+                bel1.uzs = pc1.uzs;
+                bel1.pyz = pyz;
+                bel1.pzx = pzx;
+            }
+            pc1 = pn1;
+            c1ax = n1.ax;
+            c1ay = n1.ay;
+            c1az = n1.az;
+            c1pr = n1.pr;
+            c1pi = n1.pi;
+            c1ex = n1.ex;
+            c1ey = n1.ey;
+            c1ez = n1.ez;
+        }
+    }
+}
+
+// One realization: one block per tile.  coefs[r] describes step n,
+// coefs[nreal + r] step n+1.
+template <typename T, int TY>
+__global__ void __launch_bounds__(64 * Tile2Geom<TY>::NW)
+k_step_tiled2(const RealDesc *descs, const Coef *coefs, int r, int nreal, int cz) {
+    const RealDesc d = descs[r];
+    const Coef c0 = coefs[r];
+    if (!c0.active)
+        return;
+    const Coef c1 = coefs[nreal + r];
+    tiled2_tile<T, TY>(d, c0, c1, xcd_remap(blockIdx.x, gridDim.x), cz);
+}
+
+// Tile heights of the two-step kernel (LDS: FP32 94 KB at TY = 8, FP64
+// 120 KB at TY = 4; a workgroup may hold up to 160 KB on gfx950).
+inline bool tiled2_ty_valid(bool fp64, int ty) {
+    return ty == 4 || (!fp64 && ty == 8);
+}
+
+inline void tiled2_defaults(bool fp64, int nx, int ny, int nz, int &ty, int &cz) {
+    if (ty <= 0)
+        ty = fp64 ? 4 : 8;
+    if (cz <= 0) {
+        // long chunks amortise the two extra planes of step one; aim at ~2048 blocks
+        const long tiles_xy = (long)(nx / 64) * ((ny + ty - 1) / ty);
+        long chunks = (2048 + tiles_xy - 1) / tiles_xy;
+        const long max_chunks = (nz + 31) / 32;
+        if (chunks > max_chunks)
+            chunks = max_chunks;
+        if (chunks < 1)
+            chunks = 1;
+        cz = (int)((nz + chunks - 1) / chunks);
+    }
+}
+
+template <typename T, int TY>
+hipError_t launch_tiled2_ty(const RealDesc *desc, const Coef *coef, int r, int nreal, int nx, int ny,
+                            int nz, int cz, hipStream_t stream) {
+    const long blocks = (long)(nx / 64) * ((ny + TY - 1) / TY) * ((nz + cz - 1) / cz);
+    hipLaunchKernelGGL((k_step_tiled2<T, TY>), dim3((unsigned)blocks), dim3(64 * Tile2Geom<TY>::NW),
+                       0, stream, desc, coef, r, nreal, cz);
+    return hipGetLastError();
+}
+
+// Launch the two-step kernel for realization r (nx % 64 == 0, 20-plane layout).
+inline int launch_step_tiled2(bool fp64, const RealDesc *desc, const Coef *coef, int r, int nreal,
+                              int nx, int ny, int nz, int tile_y, int chunk_z, hipStream_t stream) {
+    int ty = tile_y, cz = chunk_z;
+    tiled2_defaults(fp64, nx, ny, nz, ty, cz);
+    if (nx % 64 != 0 || !tiled2_ty_valid(fp64, ty) || cz < 1)
+        return (int)hipErrorInvalidValue;
+    hipError_t e;
+    if (fp64)
+        e = launch_tiled2_ty<double, 4>(desc, coef, r, nreal, nx, ny, nz, cz, stream);
+    else if (ty == 4)
+        e = launch_tiled2_ty<float, 4>(desc, coef, r, nreal, nx, ny, nz, cz, stream);
+    else
+        e = launch_tiled2_ty<float, 8>(desc, coef, r, nreal, nx, ny, nz, cz, stream);
+    return (int)e;
+}
+
+} // namespace ah

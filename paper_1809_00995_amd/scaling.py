@@ -22,14 +22,15 @@ import torch
 
 from . import ah as AH
 
-# name: (era p, s, core growth).  a(tau_end) = 1 and the runs start at tau = 0.  The
-# core-growth variant (s = -1 until tau_cg = tau_end / 2 with a(tau_cg) = 1, from
-# tau = 0.1 tau_end) is available but not run by default: at 512^3 with dx = 0.5 its early
-# comoving core width, sqrt(2)^-1 a/a_cg, falls below one lattice spacing, so the strings
-# are not resolved (the paper notes that s = 1 needs a larger dynamic range).
+# name: (era p, s, core growth).  Without core growth a(tau_end) = 1 and the runs start
+# at tau = 0.  With core growth s = -1 until tau_cg = tau_end / 2 and s afterwards, with
+# a(tau_cg) = 1 so that the couplings e0 a^(s-1), lambda0 a^(2(s-1)) are continuous there;
+# the comoving core width (e0 sigma)^-1 a^(-s) then grows as a until tau_cg and shrinks
+# as 1/a after it.  The run starts at tau0 = tau_end / 4, where the width is half its
+# peak, so that it stays within [dx, 2 dx] for dx = 0.5 in radiation (p = 1).
 CASES = {"radiation_s1": (1.0, 1.0, False), "radiation_s0": (1.0, 0.0, False),
          "matter_s0": (2.0, 0.0, False), "radiation_s1_core_growth": (1.0, 1.0, True)}
-DEFAULT_CASES = ("radiation_s0", "matter_s0", "radiation_s1")
+DEFAULT_CASES = ("radiation_s0", "matter_s0", "radiation_s1_core_growth")
 
 
 def evolve(n: int, era: float, s: float, seed: int, measure_every: int = 10, dx: float = 0.5,
@@ -37,7 +38,7 @@ def evolve(n: int, era: float, s: float, seed: int, measure_every: int = 10, dx:
     """One run to tau_end = n dx / 2; returns the observation series."""
     tau_end = n * dx / 2.0
     if core_growth:
-        tau0 = round(0.1 * tau_end / dt) * dt
+        tau0 = round(0.25 * tau_end / dt) * dt
         p = AH.Params(n, n, n, precision=AH.AH_FP32, dx=dx, dt=dt, tau0=tau0,
                       tau_ref=tau_end / 2, era_p=era, s=-1.0, s_late=s, tau_s=tau_end / 2,
                       seed=seed)
@@ -51,6 +52,15 @@ def evolve(n: int, era: float, s: float, seed: int, measure_every: int = 10, dx:
         obs += c.measure()
     torch.cuda.empty_cache()
     return obs
+
+
+def series(obs, n: int, dx: float = 0.5):
+    """Observation series of one run: tau, l / V_box, xi_L, xi_W, <v^2>_{L,V,rho,omega}."""
+    vbox = float(n) ** 3 * dx ** 3
+    return {"tau": [o.tau for o in obs], "l_over_v": [o.length / vbox for o in obs],
+            "xi_l": [o.xi_l for o in obs], "xi_w": [o.xi_w for o in obs],
+            "v2_l": [o.v2[0] for o in obs], "v2_v": [o.v2[1] for o in obs],
+            "v2_rho": [o.v2[2] for o in obs], "v2_w": [o.v2_eos for o in obs]}
 
 
 def fit(obs, frac_start: float = 0.5):
@@ -77,6 +87,7 @@ def main(argv=None):
     ap.add_argument("--cases", default=",".join(DEFAULT_CASES))
     ap.add_argument("--measure-every", type=int, default=10)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--series", action="store_true", help="also store each run's observation series")
     args = ap.parse_args(argv)
     result = {"n": args.n, "seeds": args.seeds, "cases": {}}
     for name in args.cases.split(","):
@@ -86,10 +97,12 @@ def main(argv=None):
             obs = evolve(args.n, era, s, seed=100 + k, measure_every=args.measure_every,
                          core_growth=cg)
             runs.append(fit(obs))
-            print(f"{name} seed {100 + k}: " + ", ".join(f"{a}={b:.4f}" for a, b in runs[-1].items()),
+            if args.series:
+                runs[-1]["series"] = series(obs, args.n)
+            print(f"{name} seed {100 + k}: " + ", ".join(f"{a}={b:.4f}" for a, b in runs[-1].items() if a != "series"),
                   flush=True)
         summary = {}
-        for key in runs[0]:
+        for key in (k for k in runs[0] if k != "series"):
             vals = np.array([r[key] for r in runs])
             summary[key] = {"mean": float(np.mean(vals)),
                             "stderr": float(np.std(vals, ddof=1) / math.sqrt(len(vals)))

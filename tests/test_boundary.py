@@ -70,6 +70,7 @@ def _init(**kw):
     (dict(tau0=-5.0), B.AH_E_DOMAIN, "a(tau"),
     (dict(init=7), B.AH_E_INVALID, "init"),
     (dict(n_end=-2), B.AH_E_INVALID, "n_end"),
+    (dict(layout=2), B.AH_E_INVALID, "layout"),
 ])
 def test_invalid_parameters_are_rejected(kw, code, text):
     rc, msg, ctx = _init(**kw)
@@ -91,6 +92,9 @@ def test_bad_extents_alignment_and_null():
     mixed = (B._Params * 2)(AH.Params(64, 8, 8)._c(), AH.Params(64, 8, 8, precision=1)._c())
     bufs = (B._Buffers * 2)(B._Buffers(4096), B._Buffers(8192))
     assert lib.ah_init(C.byref(ctx), 2, mixed, bufs, None) == B.AH_E_INVALID
+    mixed = (B._Params * 2)(AH.Params(64, 8, 8)._c(), AH.Params(64, 8, 8, layout=1)._c())
+    assert lib.ah_init(C.byref(ctx), 2, mixed, bufs, None) == B.AH_E_INVALID
+    assert "one layout" in lib.ah_last_error(None).decode()
     assert lib.ah_step(None, 1, 0, None, 0, None) == B.AH_E_INVALID
     assert lib.ah_free(None) == B.AH_OK
     assert lib.ah_error_string(B.AH_E_NONFINITE) == b"non-finite field values"

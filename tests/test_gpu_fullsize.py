@@ -2,7 +2,8 @@
 
 - 512^3 (the benchmark workload): one step of the library against the oracle
   evaluated site by site on sampled sites (tile edges in x and y, z-chunk
-  edges, lattice boundaries, random interior sites), FP32 and FP64.
+  edges, lattice boundaries, random interior sites), FP32 and FP64; and the
+  two-steps-per-pass kernel against single steps, bit for bit.
 - 256^3 radiation era, s = 1, to tau = 64 (640 steps, diagnostics every 10):
   fields after 10 steps against the oracle (FP64: 1e-12; FP32 from the
   FP32-rounded start: 1e-5 per field group), diagnostics at step 10 against
@@ -60,6 +61,32 @@ def test_512cubed_one_step_on_sampled_sites(O, prec):
         err = np.abs(got[:, cols] - ref[:, cols]).max() / scale
         print(f"  {g}: max rel err {err:.2e} over {idx.size} sites", flush=True)
         assert err < tol, g
+
+
+@pytest.mark.parametrize("prec", [AH.AH_FP32, AH.AH_FP64])
+def test_512cubed_two_step_pass_equals_single_steps(prec):
+    """The two-steps-per-pass kernel at 512^3 in its default launch shape (20-plane
+    layout): 31 steps with diagnostics every 20 from the random-phase start are
+    bit-identical to single steps in the 15-plane layout, whose one-step result is
+    checked against the oracle site by site above."""
+    n = 512
+    print(f"CASE test=512_two_step prec={prec}", flush=True)
+    base = dict(precision=prec, dx=0.5, dt=0.1, tau0=0.0, tau_ref=n * 0.5 / 2, era_p=2.0,
+                s=0.0, seed=2024)
+    runs = []
+    for layout in (AH.AH_LAYOUT_15, AH.AH_LAYOUT_20):
+        p = AH.Params(n, n, n, layout=layout, **base)
+        planes = AH.alloc_planes(p)
+        with AH.Context([p], [planes]) as c:
+            obs = c.step(31, measure_every=20)
+            runs.append((c.fields().clone(), [o[0] for o in obs]))
+        del planes
+        torch.cuda.empty_cache()
+    (f15, o15), (f20, o20) = runs
+    assert torch.equal(f15, f20)
+    for a, b in zip(o15, o20):
+        assert a.step == b.step and a.n_wind == b.n_wind
+        assert a.energy == pytest.approx(b.energy, rel=1e-12)
 
 
 def test_config_256cubed_radiation_run(O):
