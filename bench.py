@@ -53,14 +53,17 @@ def parse():
 
 
 def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15):
-    """Time `steps` steps (with the measurement cadence) after `warmup` steps.
-    Returns (site-updates/s, ms/step, mean step-kernel ms per launch, steps per
-    launch, last observation)."""
+    """Time `steps` steps with the measurement cadence after `warmup` steps,
+    then the same number of steps without diagnostics, then single launches
+    of the dominant kernel.  Returns a dict."""
     # tau_end = n dx / 2, half a light-crossing time (Sec. 2), with a(tau_end) = 1
     p = AH.Params(n, n, n, precision=prec, dx=0.5, dt=0.1, tau0=0.0, tau_ref=n * 0.5 / 2.0,
                   era_p=2.0, s=0.0, seed=2024,
                   layout=AH.AH_LAYOUT_20 if layout == 20 else AH.AH_LAYOUT_15)
-    two = layout == 20 and kernel in (AH.AH_KERNEL_AUTO, AH.AH_KERNEL_TILED2)
+    # the library's choice: pairs through the two-step kernel in the 20-plane
+    # layout (by default for FP32 only)
+    two = layout == 20 and (kernel == AH.AH_KERNEL_TILED2 or
+                            (kernel == AH.AH_KERNEL_AUTO and prec == AH.AH_FP32))
     planes = AH.alloc_planes(p)
     ctx = AH.Context([p], [planes])
     if kernel != AH.AH_KERNEL_AUTO:
@@ -69,15 +72,19 @@ def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15):
     ctx.step(warmup)
     torch.cuda.synchronize()
 
-    # whole-job throughput with the measurement cadence
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record(stream)
-    obs = ctx.step(steps, measure_every=MEASURE_EVERY)
-    t1.record(stream)
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1)
-    rate = n ** 3 * steps / (ms * 1e-3)
+    def timed(fn):
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        out = fn()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1), out
+
+    # whole-job throughput with the measurement cadence (the reported value)
+    ms, obs = timed(lambda: ctx.step(steps, measure_every=MEASURE_EVERY))
+    # and without diagnostics (from a step index of the same parity)
+    ms_nd, _ = timed(lambda: ctx.step(steps))
 
     # dominant kernel: calls that run one launch of it (one pass: one step, or
     # a pair with the two-step kernel), bracketed by events on the same stream
@@ -90,12 +97,25 @@ def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15):
         ctx.step(per)
         b.record(stream)
     torch.cuda.synchronize()
-    kms = sum(a.elapsed_time(b) for a, b in evs) / k
+    kt = sorted(a.elapsed_time(b) for a, b in evs)
     last = obs[-1][0] if obs else None
     ctx.close()
     del planes
     torch.cuda.empty_cache()
-    return rate, ms / steps, kms, per, last
+    return {"rate": n ** 3 * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+            "rate_no_diag": n ** 3 * steps / (ms_nd * 1e-3), "kernel_ms": kt[len(kt) // 2],
+            "kernel_ms_mean": sum(kt) / len(kt), "launches_timed": k, "per": per, "last": last}
+
+
+# HBM bytes per launch of the dominant kernel from the profiler's byte counters
+# (FETCH_SIZE x 2 + WRITE_SIZE x 1, factors from a 1 GiB device copy measured
+# in the same runs), for the kernel as it was profiled; the summaries and
+# commands are in profiles/.  Keyed by (dtype, layout, kernel option, lattice).
+PROFILED_TRAFFIC_BYTES = {}
+
+
+def profiled_traffic(dt, layout, kernel, n):
+    return PROFILED_TRAFFIC_BYTES.get((dt, layout, kernel, n))
 
 
 def ensemble_params(AH):
@@ -169,8 +189,9 @@ def main():
     n, K, W = args.n, args.steps, args.warmup
     other = 15 if args.layout == 20 else 20
 
-    rate32, ms32, kms32, per32, last32 = run_form(AH, torch, n, AH.AH_FP32, kern, K, W,
-                                                  args.layout)
+    f32 = run_form(AH, torch, n, AH.AH_FP32, kern, K, W, args.layout)
+    rate32, ms32, kms32, per32, last32 = (f32["rate"], f32["ms_per_step"], f32["kernel_ms"],
+                                          f32["per"], f32["last"])
     print(f"# fp32 {args.kernel} layout {args.layout}: {rate32:.4g} site-updates/s, "
           f"{ms32:.3f} ms/step, step kernel {kms32:.3f} ms per {per32}-step launch",
           file=sys.stderr, flush=True)
@@ -188,9 +209,13 @@ def main():
                    "layout": args.layout,
                    "precision": "FP32 fields and stencil, FP64 bookkeeping and reductions"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic("f32", args.layout, args.kernel, n),
                      "kernel": kname, "steps_per_launch": per32,
-                     "bytes_per_site_update": BYTES_PER_SITE["f32"], "kernel_ms": kms32},
+                     "bytes_per_site_update": BYTES_PER_SITE["f32"], "kernel_ms": kms32,
+                     "kernel_ms_mean": f32["kernel_ms_mean"],
+                     "launches_timed": f32["launches_timed"]},
+        "without_diagnostics": {"value": f32["rate_no_diag"], "steps": K},
     }
     if last32 is not None:
         line["last_obs"] = {"step": last32.step, "n_wind": last32.n_wind,
@@ -200,19 +225,20 @@ def main():
                  ("fp64", AH.AH_FP64, kern, K, W, args.layout, "f64"),
                  ("fp64_layout%d" % other, AH.AH_FP64, kern, K, W, other, "f64")]
         for name, prec, kk, steps, warm, lay, dt in forms:
-            r_, ms_, kms_, per_, _ = run_form(AH, torch, n, prec, kk, steps, warm, lay)
-            print(f"# {name}: {r_:.4g} site-updates/s", file=sys.stderr, flush=True)
-            ach = BYTES_PER_SITE[dt] * n ** 3 * per_ / (kms_ * 1e-3) / 1e9
-            line[name] = {"value": r_, "ms_per_step": ms_, "kernel_ms": kms_,
-                          "steps_per_launch": per_, "layout": lay, "achieved_GBs": ach,
-                          "frac": ach / HBM_PEAK_GBS}
+            f = run_form(AH, torch, n, prec, kk, steps, warm, lay)
+            print(f"# {name}: {f['rate']:.4g} site-updates/s", file=sys.stderr, flush=True)
+            ach = BYTES_PER_SITE[dt] * n ** 3 * f["per"] / (f["kernel_ms"] * 1e-3) / 1e9
+            line[name] = {"value": f["rate"], "ms_per_step": f["ms_per_step"],
+                          "value_without_diagnostics": f["rate_no_diag"],
+                          "kernel_ms": f["kernel_ms"], "steps_per_launch": f["per"],
+                          "layout": lay, "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}
         kp = max(10, K // 4)
-        ratep, msp, kmsp, _, _ = run_form(AH, torch, n, AH.AH_FP64, AH.AH_KERNEL_PLAIN, kp, 2)
-        print(f"# fp64 plain: {ratep:.4g} site-updates/s", file=sys.stderr, flush=True)
-        line["plain_fp64"] = {"value": ratep, "ms_per_step": msp, "kernel_ms": kmsp,
-                              "steps": kp}
-        line["speedup_fp32_vs_plain_fp64"] = rate32 / ratep
-        line["speedup_fp64_vs_plain_fp64"] = line["fp64"]["value"] / ratep
+        fp = run_form(AH, torch, n, AH.AH_FP64, AH.AH_KERNEL_PLAIN, kp, 2)
+        print(f"# fp64 plain: {fp['rate']:.4g} site-updates/s", file=sys.stderr, flush=True)
+        line["plain_fp64"] = {"value": fp["rate"], "ms_per_step": fp["ms_per_step"],
+                              "kernel_ms": fp["kernel_ms"], "steps": kp}
+        line["speedup_fp32_vs_plain_fp64"] = rate32 / fp["rate"]
+        line["speedup_fp64_vs_plain_fp64"] = line["fp64"]["value"] / fp["rate"]
     if not args.no_secondary and not args.no_ensemble:
         rb, sb, tuning = run_ensemble(AH, torch, True, 10, True)
         rs, ss, _ = run_ensemble(AH, torch, False, 0, False)

@@ -208,11 +208,13 @@ bool use_tiled(const ah_ctx *c, int r) {
 }
 
 // Unmeasured steps go in pairs through the two-step kernel: explicitly, or by
-// default in the 20-plane layout (per-realization launches only).
+// default for FP32 in the 20-plane layout (per-realization launches only).
+// In FP64 the two-step kernel holds twice the LDS and registers per site and
+// runs slower than single steps, so AUTO keeps single steps there.
 bool use_tiled2(const ah_ctx *c) {
     if (c->layout != AH_LAYOUT_20 || !tiled_ok(c))
         return false;
-    return c->kernel == AH_KERNEL_TILED2 || c->kernel == AH_KERNEL_AUTO;
+    return c->kernel == AH_KERNEL_TILED2 || (c->kernel == AH_KERNEL_AUTO && c->prec == AH_FP32);
 }
 
 // The batched kernel needs tiled shapes and one common step index (so every

@@ -69,6 +69,17 @@ template <typename T> __device__ __forceinline__ T* plane(const RealDesc &d, int
     return reinterpret_cast<T*>(d.base + (size_t)k * (size_t)d.N * sizeof(T));
 }
 
+// The same plane as a pointer into the global address space.  The planes'
+// addresses come from a descriptor in memory, so the compiler cannot infer
+// their address space and would emit flat accesses, which also count against
+// the LDS wait counter; global accesses leave a barrier free to wait for LDS
+// only while prefetched loads are in flight.
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+
+template <typename T> __device__ __forceinline__ gptr<T> gplane(const RealDesc &d, int k) {
+    return (gptr<T>)(d.base + (size_t)k * (size_t)d.N * sizeof(T));
+}
+
 // Plane of field f (0..9) in copy `parity` (0 or 1).  AH_LAYOUT_15: copy 1
 // of phi and A is planes 10-14 and Pi, E have one plane each (updated in
 // place); AH_LAYOUT_20: copy 1 of every field is plane f + 10.
@@ -92,6 +103,16 @@ __device__ __forceinline__ void sincos_t(float x, float *s, float *c) { sincosf(
 __device__ __forceinline__ void sincos_t(double x, double *s, double *c) { sincos(x, s, c); }
 __device__ __forceinline__ float sin_t(float x) { return sinf(x); }
 __device__ __forceinline__ double sin_t(double x) { return sin(x); }
+
+// Workgroup barrier that orders LDS only: each wave waits for its own LDS
+// accesses, not for its global loads, so loads issued ahead of the barrier
+// (prefetches of the next plane) stay in flight across it.  For kernels that
+// share data between waves through LDS alone.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 // ---------------------------------------------------------------- reductions
 // Sum over a 64-lane wavefront; lane 0 ends with the total.

@@ -212,19 +212,21 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
     const int q = G::li(lx, ly);
 
     const int par = c.parity, L = d.layout;
-    const T *phr = plane<T>(d, field_plane(0, par, L));
-    const T *phi = plane<T>(d, field_plane(1, par, L));
-    const T *A0 = plane<T>(d, field_plane(4, par, L));
-    const T *A1 = plane<T>(d, field_plane(5, par, L));
-    const T *A2 = plane<T>(d, field_plane(6, par, L));
-    const T *pir = plane<T>(d, field_plane(2, par, L)), *pii = plane<T>(d, field_plane(3, par, L));
-    const T *E0 = plane<T>(d, field_plane(7, par, L)), *E1 = plane<T>(d, field_plane(8, par, L));
-    const T *E2 = plane<T>(d, field_plane(9, par, L));
+    const gptr<const T> phr = gplane<const T>(d, field_plane(0, par, L));
+    const gptr<const T> phi = gplane<const T>(d, field_plane(1, par, L));
+    const gptr<const T> A0 = gplane<const T>(d, field_plane(4, par, L));
+    const gptr<const T> A1 = gplane<const T>(d, field_plane(5, par, L));
+    const gptr<const T> A2 = gplane<const T>(d, field_plane(6, par, L));
+    const gptr<const T> pir = gplane<const T>(d, field_plane(2, par, L));
+    const gptr<const T> pii = gplane<const T>(d, field_plane(3, par, L));
+    const gptr<const T> E0 = gplane<const T>(d, field_plane(7, par, L));
+    const gptr<const T> E1 = gplane<const T>(d, field_plane(8, par, L));
+    const gptr<const T> E2 = gplane<const T>(d, field_plane(9, par, L));
     // the new state: phi, A always to the other copy; Pi, E in place in the
     // 15-plane layout (each thread reads them only at its own site)
-    T *o[10];
+    gptr<T> o[10];
     for (int f = 0; f < 10; ++f)
-        o[f] = plane<T>(d, field_plane(f, par ^ 1, L));
+        o[f] = gplane<T>(d, field_plane(f, par ^ 1, L));
 
     const StepK<T> K = step_k<T>(d, c);
     const T s2 = K.s2;

@@ -26,6 +26,8 @@
 // S_{n+1} instead.
 #pragma once
 
+#include <type_traits>
+
 #include "k_step_tiled.hpp"
 
 namespace ah {
@@ -214,11 +216,11 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
     const int rgx = wrap_mod(x0 + rx, nx), rgy = wrap_mod(y0 + ry, ny);
 
     const int par = c0.parity, L = d.layout;
-    const T *in[10];
-    T *out[10];
+    gptr<const T> in[10];
+    gptr<T> out[10];
     for (int f = 0; f < 10; ++f) {
-        in[f] = plane<T>(d, field_plane(f, par, L));
-        out[f] = plane<T>(d, field_plane(f, par ^ 1, L));
+        in[f] = gplane<const T>(d, field_plane(f, par, L));
+        out[f] = gplane<T>(d, field_plane(f, par ^ 1, L));
     }
     const StepK<T> K0 = step_k<T>(d, c0), K1 = step_k<T>(d, c1);
 
@@ -246,8 +248,8 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
 
     // ---- prologue: S_n planes z0-2 (buffer 1) and z0-1 (buffer 0)
     const int za = zwrap(z0 - 2), zb = zwrap(z0 - 1);
-    Raw rcur, rnxt;
-    Phasors<T> pcur, pnxt;
+    Raw rcur;
+    Phasors<T> pcur;
     Below<T> bel;
     {
         const Raw rb = load_raw(own_site(za));
@@ -260,7 +262,7 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
         if (has1)
             put_phasors<T, G::S2>(sa[0], q2, pcur);
         stage_ring(0, zb);
-        __syncthreads();
+        lds_barrier();
         bel.pyz = bel.pzx = 0;
         if (has1)
             base_plaquettes<T, G::W2, G::S2>(sa[1], q2, pb, pcur, bel.pyz, bel.pzx);
@@ -268,124 +270,145 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
         bel.pm = pb.pm;
         bel.uzc = pb.uzc;
         bel.uzs = pb.uzs;
-        __syncthreads();
+        lds_barrier();
     }
 
-    // S_{n+1} at the own site: cur1 (plane p), the carried values below it
-    Phasors<T> pc1;
-    T c1ax = 0, c1ay = 0, c1az = 0, c1pr = 0, c1pi = 0, c1ex = 0, c1ey = 0, c1ez = 0;
-    Below<T> bel1;
-    bel1.pr = bel1.pm = bel1.uzc = bel1.uzs = bel1.pyz = bel1.pzx = 0;
-    pc1.pr = pc1.pm = pc1.uxc = pc1.uxs = pc1.uyc = pc1.uys = pc1.uzc = pc1.uzs = 0;
-
-    const int nk = (z1 - z0) + 2;
-    for (int k = 0; k < nk; ++k) {
-        const int zs = zwrap(z0 - 1 + k);          // plane of step one
-        const int zn = zwrap(z0 + k);              // plane zs + 1
-        const int cb = k & 1, nb = cb ^ 1;
-        const int s = own_site(zs);
-        // (a) stage S_n at zs+1; read the momenta of S_n at zs
-        T pr0 = 0, pi0 = 0, ex0 = 0, ey0 = 0, ez0 = 0;
+    // The global reads of iteration k (S_n at plane zs+1 on the own site and
+    // the outer ring, the momenta of S_n at zs) are issued one iteration
+    // ahead, so their latency hides behind the previous plane's two steps.
+    Raw f_own{}, f_ring{};
+    T f_pr0 = 0, f_pi0 = 0, f_ex0 = 0, f_ey0 = 0, f_ez0 = 0;
+    auto prefetch = [&](int k) {
+        const int zs = zwrap(z0 - 1 + k), zn = zwrap(z0 + k);
         if (has1) {
-            pr0 = in[2][s];
-            pi0 = in[3][s];
-            ex0 = in[7][s];
-            ey0 = in[8][s];
-            ez0 = in[9][s];
-            rnxt = load_raw(own_site(zn));
-            pnxt = make_phasors(rnxt.pr, rnxt.pm, rnxt.ax, rnxt.ay, rnxt.az);
-            put_phasors<T, G::S2>(sa[nb], q2, pnxt);
+            const int s = own_site(zs);
+            f_pr0 = in[2][s];
+            f_pi0 = in[3][s];
+            f_ex0 = in[7][s];
+            f_ey0 = in[8][s];
+            f_ez0 = in[9][s];
+            f_own = load_raw(own_site(zn));
         }
-        stage_ring(nb, zn);
-        __syncthreads();
+        if (stager)
+            f_ring = load_raw(rgx + nx * (rgy + ny * zn));
+    };
+    auto store_state = [&](const SiteNew<T> &v, int s) {
+        __builtin_nontemporal_store(v.pr, out[2] + s);
+        __builtin_nontemporal_store(v.pi, out[3] + s);
+        __builtin_nontemporal_store(v.ex, out[7] + s);
+        __builtin_nontemporal_store(v.ey, out[8] + s);
+        __builtin_nontemporal_store(v.ez, out[9] + s);
+        __builtin_nontemporal_store(v.qr, out[0] + s);
+        __builtin_nontemporal_store(v.qi, out[1] + s);
+        __builtin_nontemporal_store(v.ax, out[4] + s);
+        __builtin_nontemporal_store(v.ay, out[5] + s);
+        __builtin_nontemporal_store(v.az, out[6] + s);
+    };
+
+    // Own-site values of one plane: S_n (raw fields and phasors) and S_{n+1}
+    // (new values and phasors).  The loop is unrolled by two with the sets
+    // alternating roles, so the plane-to-plane hand-over needs no copies and
+    // the LDS buffer of each half is a constant.
+    struct SnSet {
+        Raw r;
+        Phasors<T> p;
+    };
+    struct S1Set {
+        SiteNew<T> v;
+        Phasors<T> p;
+    };
+    SnSet sA, sB;
+    S1Set uA{}, uB{};
+    sA.r = rcur;
+    sA.p = pcur;
+    Below<T> bel1{};
+
+    // Iteration k: step one on plane zs = z0-1+k (S_n in sa[CB], plane zs+1
+    // goes to sa[CB^1]), S_{n+1} of plane zs to sb[CB]; step two on plane zs-1
+    // (S_{n+1} in sb[CB^1] and sb[CB]).  cur/nxt: own S_n at zs, zs+1; c1/n1:
+    // own S_{n+1} at zs-1, zs.
+    const int nk = (z1 - z0) + 2;
+    auto body = [&](auto cbc, int k, SnSet &cur, SnSet &nxt, S1Set &c1, S1Set &n1) {
+        constexpr int CB = decltype(cbc)::value, NB = CB ^ 1;
+        const int zs = zwrap(z0 - 1 + k);
+        // (a) stage S_n at zs+1 from the prefetched values; start the next reads
+        const T pr0 = f_pr0, pi0 = f_pi0, ex0 = f_ex0, ey0 = f_ey0, ez0 = f_ez0;
+        nxt.r = f_own;
+        if (has1) {
+            nxt.p = make_phasors(nxt.r.pr, nxt.r.pm, nxt.r.ax, nxt.r.ay, nxt.r.az);
+            put_phasors<T, G::S2>(sa[NB], q2, nxt.p);
+        }
+        if (stager)
+            put_phasors<T, G::S2>(sa[NB], rq, make_phasors(f_ring.pr, f_ring.pm, f_ring.ax,
+                                                           f_ring.ay, f_ring.az));
+        if (k + 1 < nk)
+            prefetch(k + 1);
+        lds_barrier();
 
         // (b) step one at (own R1 site, zs)
-        SiteNew<T> n1{};
-        Phasors<T> pn1{};
         if (has1) {
             T pyz, pzx;
-            const Stencil<T> st = gather<T, G::W2, G::S2>(sa[cb], sa[nb], q2, pcur, rcur.ax, rcur.ay,
-                                                          rcur.az, pnxt, bel, pr0, pi0, ex0, ey0,
-                                                          ez0, pyz, pzx);
-            n1 = leapfrog_site(st, K0);
-            bel.pr = pcur.pr;
-            bel.pm = pcur.pm;
-            bel.uzc = pcur.uzc;
-            bel.uzs = pcur.uzs;
+            const Stencil<T> st = gather<T, G::W2, G::S2>(sa[CB], sa[NB], q2, cur.p, cur.r.ax,
+                                                          cur.r.ay, cur.r.az, nxt.p, bel, pr0,
+                                                          pi0, ex0, ey0, ez0, pyz, pzx);
+            n1.v = leapfrog_site(st, K0);
+            bel.pr = cur.p.pr;
+            bel.pm = cur.p.pm;
+            bel.uzc = cur.p.uzc;
+            bel.uzs = cur.p.uzs;
             bel.pyz = pyz;
             bel.pzx = pzx;
-            rcur = rnxt;
-            pcur = pnxt;
             if (two) {
-                pn1 = make_phasors(n1.qr, n1.qi, n1.ax, n1.ay, n1.az);
-                put_phasors<T, G::S1>(sb[cb], q1, pn1);
+                n1.p = make_phasors(n1.v.qr, n1.v.qi, n1.v.ax, n1.v.ay, n1.v.az);
+                put_phasors<T, G::S1>(sb[CB], q1, n1.p);
             }
         }
         if (!two) {
             // one step only: the tile's S_{n+1} is final
-            if (owner && k >= 1 && k <= z1 - z0) {
-                __builtin_nontemporal_store(n1.pr, out[2] + s);
-                __builtin_nontemporal_store(n1.pi, out[3] + s);
-                __builtin_nontemporal_store(n1.ex, out[7] + s);
-                __builtin_nontemporal_store(n1.ey, out[8] + s);
-                __builtin_nontemporal_store(n1.ez, out[9] + s);
-                __builtin_nontemporal_store(n1.qr, out[0] + s);
-                __builtin_nontemporal_store(n1.qi, out[1] + s);
-                __builtin_nontemporal_store(n1.ax, out[4] + s);
-                __builtin_nontemporal_store(n1.ay, out[5] + s);
-                __builtin_nontemporal_store(n1.az, out[6] + s);
-            }
-            __syncthreads();
-            continue;
+            if (owner && k >= 1 && k <= z1 - z0)
+                store_state(n1.v, own_site(zs));
+            lds_barrier();
+            return;
         }
-        __syncthreads();
+        lds_barrier();
 
-        // (c) step two at (tile site, p = zs - 1), one plane behind
+        // (c) step two at (tile site, zs - 1), one plane behind
         if (inner) {
             if (k == 1) {
                 // carried values of plane z0-1 for the first plane of step two
-                base_plaquettes<T, G::W1, G::S1>(sb[0], q1, pc1, pn1, bel1.pyz, bel1.pzx);
-                bel1.pr = pc1.pr;
-                bel1.pm = pc1.pm;
-                bel1.uzc = pc1.uzc;
-                bel1.uzs = pc1.uzs;
+                base_plaquettes<T, G::W1, G::S1>(sb[NB], q1, c1.p, n1.p, bel1.pyz, bel1.pzx);
+                bel1.pr = c1.p.pr;
+                bel1.pm = c1.p.pm;
+                bel1.uzc = c1.p.uzc;
+                bel1.uzs = c1.p.uzs;
             } else if (k >= 2) {
                 T pyz, pzx;
-                const Stencil<T> st = gather<T, G::W1, G::S1>(sb[nb], sb[cb], q1, pc1, c1ax, c1ay,
-                                                              c1az, pn1, bel1, c1pr, c1pi, c1ex,
-                                                              c1ey, c1ez, pyz, pzx);
+                const Stencil<T> st = gather<T, G::W1, G::S1>(sb[NB], sb[CB], q1, c1.p, c1.v.ax,
+                                                              c1.v.ay, c1.v.az, n1.p, bel1,
+                                                              c1.v.pr, c1.v.pi, c1.v.ex,
+                                                              c1.v.ey, c1.v.ez, pyz, pzx);
                 const SiteNew<T> n2 = leapfrog_site(st, K1);
-                if (owner) {
-                    const int sp = own_site(zwrap(zs - 1));
-                    __builtin_nontemporal_store(n2.pr, out[2] + sp);
-                    __builtin_nontemporal_store(n2.pi, out[3] + sp);
-                    __builtin_nontemporal_store(n2.ex, out[7] + sp);
-                    __builtin_nontemporal_store(n2.ey, out[8] + sp);
-                    __builtin_nontemporal_store(n2.ez, out[9] + sp);
-                    __builtin_nontemporal_store(n2.qr, out[0] + sp);
-                    __builtin_nontemporal_store(n2.qi, out[1] + sp);
-                    __builtin_nontemporal_store(n2.ax, out[4] + sp);
-                    __builtin_nontemporal_store(n2.ay, out[5] + sp);
-                    __builtin_nontemporal_store(n2.az, out[6] + sp);
-                }
-                bel1.pr = pc1.pr;
-                bel1.pm = pc1.pm;
-                bel1.uzc = pc1.uzc;
-                bel1.uzs = pc1.uzs;
+                if (owner)
+                    store_state(n2, own_site(zwrap(zs - 1)));
+                bel1.pr = c1.p.pr;
+                bel1.pm = c1.p.pm;
+                bel1.uzc = c1.p.uzc;
+                bel1.uzs = c1.p.uzs;
                 bel1.pyz = pyz;
                 bel1.pzx = pzx;
             }
-            pc1 = pn1;
-            c1ax = n1.ax;
-            c1ay = n1.ay;
-            c1az = n1.az;
-            c1pr = n1.pr;
-            c1pi = n1.pi;
-            c1ex = n1.ex;
-            c1ey = n1.ey;
-            c1ez = n1.ez;
         }
+    };
+    using C0 = std::integral_constant<int, 0>;
+    using C1 = std::integral_constant<int, 1>;
+    prefetch(0);
+    int k = 0;
+    for (; k + 1 < nk; k += 2) {
+        body(C0{}, k, sA, sB, uB, uA);
+        body(C1{}, k + 1, sB, sA, uA, uB);
     }
+    if (k < nk)
+        body(C0{}, k, sA, sB, uB, uA);
 }
 
 // One realization: one block per tile.  coefs[r] describes step n,
