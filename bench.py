@@ -111,7 +111,10 @@ def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15):
 # (FETCH_SIZE x 2 + WRITE_SIZE x 1, factors from a 1 GiB device copy measured
 # in the same runs), for the kernel as it was profiled; the summaries and
 # commands are in profiles/.  Keyed by (dtype, layout, kernel option, lattice).
-PROFILED_TRAFFIC_BYTES = {}
+PROFILED_TRAFFIC_BYTES = {
+    # k_step_tiled2<float, 8>, profiles/step_tiled2_512cubed.md
+    ("f32", 20, "auto", 512): 12.05e9,
+}
 
 
 def profiled_traffic(dt, layout, kernel, n):
@@ -217,6 +220,10 @@ def main():
                      "launches_timed": f32["launches_timed"]},
         "without_diagnostics": {"value": f32["rate_no_diag"], "steps": K},
     }
+    tr = line["roofline"]["traffic"]
+    if tr is not None:
+        # measured HBM bytes per launch (profiler counters) at this run's kernel time
+        line["roofline"]["traffic_GBs"] = tr / (kms32 * 1e-3) / 1e9
     if last32 is not None:
         line["last_obs"] = {"step": last32.step, "n_wind": last32.n_wind,
                             "xi_w": last32.xi_w, "v2_L": last32.v2[0]}

@@ -631,6 +631,7 @@ int ah_step(ah_ctx *c, int64_t nsteps, int32_t measure_every, ah_obs *out, int64
     const bool two = use_tiled2(c) && !batch_ok(c);
     while (i < nsteps) {
         if (next < meas.size() && meas_at[next] == i) {
+            // measured states take a single-step pass with the fused measurement
             TRY(launch_pass(c, 1, c->d_slots + next * c->nreal, meas[next].data(), true));
             mirror_pass(c, 1);
             ++next;

@@ -176,6 +176,127 @@ __device__ __forceinline__ int wrap_mod(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
+// Per-thread FP64 accumulators of one measurement of S_n (Eqs. (9)-(12)),
+// with the a-dependent weights of the conformal densities.
+struct MeasAcc {
+    double s[A_COUNT];
+    int c[C_COUNT];        // per thread at most 3 per plane of one column: 32 bits suffice
+    double a2, g, h, idx2, s2;
+};
+
+__device__ __forceinline__ void meas_init(MeasAcc &m, const RealDesc &d, const Coef &c) {
+    for (int k = 0; k < A_COUNT; ++k)
+        m.s[k] = 0.0;
+    for (int k = 0; k < C_COUNT; ++k)
+        m.c[k] = 0;
+    m.a2 = c.a_0 * c.a_0;
+    m.g = pow(c.a_0, 2.0 * (1.0 - c.s_0)) / (2.0 * d.e0 * d.e0);
+    m.h = d.lambda0 * pow(c.a_0, 2.0 + 2.0 * c.s_0);
+    m.idx2 = 1.0 / (d.dx * d.dx);
+    m.s2 = d.sigma * d.sigma;
+}
+
+// What the measurement of site x reads: its fields and phasors, phi at
+// x+x, x+y, x+z, the phasors of the other links of its three forward
+// plaquettes, and arg(phi) (FP64) and the raw link angles at the corners of
+// those plaquettes.
+template <typename T> struct MeasSite {
+    T pr, pm, pr0, pi0, ax, ay, az, ex0, ey0, ez0;
+    T uxc, uxs, uyc, uys, uzc, uzs;
+    T pr_xp, pi_xp, pr_yp, pi_yp, pr_zp, pi_zp;
+    T uyc_xp, uys_xp, uzc_xp, uzs_xp, uxc_yp, uxs_yp, uzc_yp, uzs_yp, uxc_zp, uxs_zp, uyc_zp, uys_zp;
+    double th, th_xp, th_yp, th_xpyp, th_zp, th_xpzp, th_ypzp;
+    double ay_xp, az_xp, ax_yp, az_yp, ax_zp, ay_zp;
+};
+
+// Add site x of S_n to the accumulators: the densities of Eqs. (9)-(10), the
+// pressure of Eq. (12), and the windings of its xy, yz, zx plaquettes
+// (Eq. (11)) from the wrap counts of their links; w3 receives the windings.
+template <typename T>
+__device__ __forceinline__ void measure_site(MeasAcc &m, const MeasSite<T> &v, int (&w3)[3]) {
+    const bool finite = isfinite((double)v.pr) && isfinite((double)v.pm) &&
+                        isfinite((double)v.pr0) && isfinite((double)v.pi0) &&
+                        isfinite((double)v.ax) && isfinite((double)v.ay) &&
+                        isfinite((double)v.az) && isfinite((double)v.ex0) &&
+                        isfinite((double)v.ey0) && isfinite((double)v.ez0);
+    w3[0] = w3[1] = w3[2] = 0;
+    if (!finite) {
+        m.c[C_NONFIN] += 1;
+        return;
+    }
+    const T pr = v.pr, pm = v.pm;
+    const T gxr = v.uxc * v.pr_xp - v.uxs * v.pi_xp - pr;
+    const T gxi = v.uxc * v.pi_xp + v.uxs * v.pr_xp - pm;
+    const T gyr = v.uyc * v.pr_yp - v.uys * v.pi_yp - pr;
+    const T gyi = v.uyc * v.pi_yp + v.uys * v.pr_yp - pm;
+    const T gzr = v.uzc * v.pr_zp - v.uzs * v.pi_zp - pr;
+    const T gzi = v.uzc * v.pi_zp + v.uzs * v.pr_zp - pm;
+    const double idx2 = m.idx2, ma2 = m.a2, mg = m.g, mh = m.h;
+    const double K = (double)v.pr0 * v.pr0 + (double)v.pi0 * v.pi0;
+    const double Gr = idx2 * ((double)gxr * gxr + (double)gxi * gxi + (double)gyr * gyr +
+                              (double)gyi * gyi + (double)gzr * gzr + (double)gzi * gzi);
+    const double EE = idx2 * ((double)v.ex0 * v.ex0 + (double)v.ey0 * v.ey0 + (double)v.ez0 * v.ez0);
+    const T oxy = plaq_omc(v.uxc, v.uxs, v.uyc_xp, v.uys_xp, v.uxc_yp, v.uxs_yp, v.uyc, v.uys);
+    const T oyz = plaq_omc(v.uyc, v.uys, v.uzc_yp, v.uzs_yp, v.uyc_zp, v.uys_zp, v.uzc, v.uzs);
+    const T ozx = plaq_omc(v.uzc, v.uzs, v.uxc_zp, v.uxs_zp, v.uzc_xp, v.uzs_xp, v.uxc, v.uxs);
+    const double BB = 2.0 * idx2 * idx2 * ((double)oxy + (double)oyz + (double)ozx);
+    const double vv = (double)pr * pr + (double)pm * pm - m.s2;
+    const double V = 0.25 * vv * vv;
+    const double lag = ma2 * K - ma2 * Gr + mg * (EE - BB) - mh * V;
+    const double rho = ma2 * K + ma2 * Gr + mg * (EE + BB) + mh * V;
+    const double pres = ma2 * K - ma2 * Gr / 3.0 + mg * (EE + BB) / 3.0 - mh * V;
+    m.s[A_KIN] += ma2 * K;
+    m.s[A_GRAD] += ma2 * Gr;
+    m.s[A_ELEC] += mg * EE;
+    m.s[A_MAG] += mg * BB;
+    m.s[A_POT] += mh * V;
+    m.s[A_LAG] += lag;
+    m.s[A_NUM_L] += K * lag;
+    m.s[A_NUM_V] += K * V;
+    m.s[A_NUM_R] += K * rho;
+    m.s[A_DEN_L] += Gr * lag;
+    m.s[A_DEN_V] += Gr * V;
+    m.s[A_DEN_R] += Gr * rho;
+    m.s[A_PRES] += pres;
+    m.s[A_PRES_L] += pres * lag;
+    m.s[A_RHO_L] += rho * lag;
+
+    // winding (Eq. (11)) from link wrap counts
+    const double ax = v.ax, ay = v.ay, az = v.az;
+    const int mx = wrap_count(v.th_xp - v.th + ax);
+    const int my = wrap_count(v.th_yp - v.th + ay);
+    const int mz = wrap_count(v.th_zp - v.th + az);
+    const int my_xp = wrap_count(v.th_xpyp - v.th_xp + v.ay_xp);
+    const int mx_yp = wrap_count(v.th_xpyp - v.th_yp + v.ax_yp);
+    const int mz_yp = wrap_count(v.th_ypzp - v.th_yp + v.az_yp);
+    const int my_zp = wrap_count(v.th_ypzp - v.th_zp + v.ay_zp);
+    const int mx_zp = wrap_count(v.th_xpzp - v.th_zp + v.ax_zp);
+    const int mz_xp = wrap_count(v.th_xpzp - v.th_xp + v.az_xp);
+    w3[0] = -(mx + my_xp - mx_yp - my);
+    w3[1] = -(my + mz_yp - my_zp - mz);
+    w3[2] = -(mz + mx_zp - mz_xp - mx);
+    for (int k = 0; k < 3; ++k) {
+        m.c[C_W0 + k] += w3[k];
+        m.c[C_N0 + k] += w3[k] < 0 ? -w3[k] : w3[k];
+        m.c[C_PIERCED] += w3[k] != 0 ? 1 : 0;
+    }
+}
+
+// Block-wide reduction of the accumulators into the measurement slot; every
+// thread of the block (NW wavefronts) calls it.
+template <int NW>
+__device__ __forceinline__ void meas_commit(MeasAcc &m, Slot *slot, const Coef &c, bool first) {
+    if (first && threadIdx.x == 0) {
+        slot->c = c;
+        slot->measured = 1;
+    }
+    unsigned long long cnt64[C_COUNT];
+    for (int k = 0; k < C_COUNT; ++k)
+        cnt64[k] = (unsigned long long)(long long)m.c[k];   // two's complement for W sums
+    block_accumulate<A_COUNT, C_COUNT, NW>(m.s, cnt64, slot->acc.s, slot->acc.c);
+    __syncthreads();   // the reduction's LDS is reused by the next tile of a batch
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (block b on XCD
 // b % 8).  This bijection of [0, nb) gives XCD i the contiguous run
 // [start_i, start_i + count_i) of tile numbers, so tiles that share halo rows
@@ -229,22 +350,11 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
         o[f] = gplane<T>(d, field_plane(f, par ^ 1, L));
 
     const StepK<T> K = step_k<T>(d, c);
-    const T s2 = K.s2;
 
-    // measurement constants and per-thread FP64 accumulators
-    double msum[A_COUNT];
-    int mcnt[C_COUNT];       // per thread at most 3 per plane of one column: 32 bits suffice
-    double ma2 = 0.0, mg = 0.0, mh = 0.0, idx2 = 0.0;
-    if (MEAS) {
-        for (int k = 0; k < A_COUNT; ++k)
-            msum[k] = 0.0;
-        for (int k = 0; k < C_COUNT; ++k)
-            mcnt[k] = 0;
-        ma2 = c.a_0 * c.a_0;
-        mg = pow(c.a_0, 2.0 * (1.0 - c.s_0)) / (2.0 * d.e0 * d.e0);
-        mh = d.lambda0 * pow(c.a_0, 2.0 + 2.0 * c.s_0);
-        idx2 = 1.0 / (d.dx * d.dx);
-    }
+    // per-thread FP64 accumulators of the measuring modes
+    MeasAcc macc;
+    if (MEAS)
+        meas_init(macc, d, c);
 
     auto load_site = [&](int s, SiteV<T> &v) {
         v.pr = phr[s];
@@ -382,76 +492,25 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
 
         if (MEAS && owner) {
             // Eqs. (9)-(12) for the site of S_n read above
-            const bool finite = isfinite((double)pr) && isfinite((double)pm) &&
-                                isfinite((double)pr0) && isfinite((double)pi0) &&
-                                isfinite((double)cur.ax) && isfinite((double)cur.ay) &&
-                                isfinite((double)cur.az) && isfinite((double)ex0) &&
-                                isfinite((double)ey0) && isfinite((double)ez0);
-            int w3[3] = { 0, 0, 0 };
-            if (!finite) {
-                mcnt[C_NONFIN] += 1;
-            } else {
-                const T gxr = cur.uxc * pr_xp - cur.uxs * pi_xp - pr;
-                const T gxi = cur.uxc * pi_xp + cur.uxs * pr_xp - pm;
-                const T gyr = cur.uyc * pr_yp - cur.uys * pi_yp - pr;
-                const T gyi = cur.uyc * pi_yp + cur.uys * pr_yp - pm;
-                const T gzr = cur.uzc * nxt.pr - cur.uzs * nxt.pm - pr;
-                const T gzi = cur.uzc * nxt.pm + cur.uzs * nxt.pr - pm;
-                const double K = (double)pr0 * pr0 + (double)pi0 * pi0;
-                const double Gr = idx2 * ((double)gxr * gxr + (double)gxi * gxi + (double)gyr * gyr +
-                                          (double)gyi * gyi + (double)gzr * gzr + (double)gzi * gzi);
-                const double EE = idx2 * ((double)ex0 * ex0 + (double)ey0 * ey0 + (double)ez0 * ez0);
-                const T oxy = plaq_omc(cur.uxc, cur.uxs, uyc_xp, uys_xp, uxc_yp, uxs_yp, cur.uyc, cur.uys);
-                const T oyz = plaq_omc(cur.uyc, cur.uys, uzc_yp, uzs_yp, nxt.uyc, nxt.uys, cur.uzc, cur.uzs);
-                const T ozx = plaq_omc(cur.uzc, cur.uzs, nxt.uxc, nxt.uxs, uzc_xp, uzs_xp, cur.uxc, cur.uxs);
-                const double BB = 2.0 * idx2 * idx2 * ((double)oxy + (double)oyz + (double)ozx);
-                const double vv = (double)pr * pr + (double)pm * pm - (double)s2;
-                const double V = 0.25 * vv * vv;
-                const double lag = ma2 * K - ma2 * Gr + mg * (EE - BB) - mh * V;
-                const double rho = ma2 * K + ma2 * Gr + mg * (EE + BB) + mh * V;
-                const double pres = ma2 * K - ma2 * Gr / 3.0 + mg * (EE + BB) / 3.0 - mh * V;
-                msum[A_KIN] += ma2 * K;
-                msum[A_GRAD] += ma2 * Gr;
-                msum[A_ELEC] += mg * EE;
-                msum[A_MAG] += mg * BB;
-                msum[A_POT] += mh * V;
-                msum[A_LAG] += lag;
-                msum[A_NUM_L] += K * lag;
-                msum[A_NUM_V] += K * V;
-                msum[A_NUM_R] += K * rho;
-                msum[A_DEN_L] += Gr * lag;
-                msum[A_DEN_V] += Gr * V;
-                msum[A_DEN_R] += Gr * rho;
-                msum[A_PRES] += pres;
-                msum[A_PRES_L] += pres * lag;
-                msum[A_RHO_L] += rho * lag;
-
-                // winding (Eq. (11)) from link wrap counts
-                const double t0 = cur.th, t_xp = lth[cb][q + 1], t_yp = lth[cb][q + G::W];
-                const double t_xpyp = lth[cb][q + 1 + G::W];
-                const double t_zp = nxt.th, t_xpzp = lth[nb_][q + 1], t_ypzp = lth[nb_][q + G::W];
-                const double ax = cur.ax, ay = cur.ay, az = cur.az;
-                const double ay_xp = lar[cb][1][q + 1], az_xp = lar[cb][2][q + 1];
-                const double ax_yp = lar[cb][0][q + G::W], az_yp = lar[cb][2][q + G::W];
-                const double ax_zp = nxt.ax, ay_zp = nxt.ay;
-                const int mx = wrap_count(t_xp - t0 + ax);
-                const int my = wrap_count(t_yp - t0 + ay);
-                const int mz = wrap_count(t_zp - t0 + az);
-                const int my_xp = wrap_count(t_xpyp - t_xp + ay_xp);
-                const int mx_yp = wrap_count(t_xpyp - t_yp + ax_yp);
-                const int mz_yp = wrap_count(t_ypzp - t_yp + az_yp);
-                const int my_zp = wrap_count(t_ypzp - t_zp + ay_zp);
-                const int mx_zp = wrap_count(t_xpzp - t_zp + ax_zp);
-                const int mz_xp = wrap_count(t_xpzp - t_xp + az_xp);
-                w3[0] = -(mx + my_xp - mx_yp - my);
-                w3[1] = -(my + mz_yp - my_zp - mz);
-                w3[2] = -(mz + mx_zp - mz_xp - mx);
-                for (int k = 0; k < 3; ++k) {
-                    mcnt[C_W0 + k] += w3[k];
-                    mcnt[C_N0 + k] += w3[k] < 0 ? -w3[k] : w3[k];
-                    mcnt[C_PIERCED] += w3[k] != 0 ? 1 : 0;
-                }
-            }
+            MeasSite<T> mv;
+            mv.pr = pr; mv.pm = pm; mv.pr0 = pr0; mv.pi0 = pi0;
+            mv.ax = cur.ax; mv.ay = cur.ay; mv.az = cur.az;
+            mv.ex0 = ex0; mv.ey0 = ey0; mv.ez0 = ez0;
+            mv.uxc = cur.uxc; mv.uxs = cur.uxs; mv.uyc = cur.uyc; mv.uys = cur.uys;
+            mv.uzc = cur.uzc; mv.uzs = cur.uzs;
+            mv.pr_xp = pr_xp; mv.pi_xp = pi_xp; mv.pr_yp = pr_yp; mv.pi_yp = pi_yp;
+            mv.pr_zp = nxt.pr; mv.pi_zp = nxt.pm;
+            mv.uyc_xp = uyc_xp; mv.uys_xp = uys_xp; mv.uzc_xp = uzc_xp; mv.uzs_xp = uzs_xp;
+            mv.uxc_yp = uxc_yp; mv.uxs_yp = uxs_yp; mv.uzc_yp = uzc_yp; mv.uzs_yp = uzs_yp;
+            mv.uxc_zp = nxt.uxc; mv.uxs_zp = nxt.uxs; mv.uyc_zp = nxt.uyc; mv.uys_zp = nxt.uys;
+            mv.th = cur.th; mv.th_xp = lth[cb][q + 1]; mv.th_yp = lth[cb][q + G::W];
+            mv.th_xpyp = lth[cb][q + 1 + G::W];
+            mv.th_zp = nxt.th; mv.th_xpzp = lth[nb_][q + 1]; mv.th_ypzp = lth[nb_][q + G::W];
+            mv.ay_xp = lar[cb][1][q + 1]; mv.az_xp = lar[cb][2][q + 1];
+            mv.ax_yp = lar[cb][0][q + G::W]; mv.az_yp = lar[cb][2][q + G::W];
+            mv.ax_zp = nxt.ax; mv.ay_zp = nxt.ay;
+            int w3[3];
+            measure_site(macc, mv, w3);
             if (MODE == MODE_MEASURE && wind)
                 for (int k = 0; k < 3; ++k)
                     wind[(size_t)k * (size_t)d.N + s] = (int8_t)w3[k];
@@ -467,17 +526,8 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
         __syncthreads();
     }
 
-    if (MEAS) {
-        if (tile == 0 && threadIdx.x == 0) {
-            slot->c = c;
-            slot->measured = 1;
-        }
-        unsigned long long cnt64[C_COUNT];
-        for (int k = 0; k < C_COUNT; ++k)
-            cnt64[k] = (unsigned long long)(long long)mcnt[k];   // two's complement for W sums
-        block_accumulate<A_COUNT, C_COUNT, TY>(msum, cnt64, slot->acc.s, slot->acc.c);
-        __syncthreads();   // the reduction's LDS is reused by the next tile of a batch
-    }
+    if (MEAS)
+        meas_commit<TY>(macc, slot, c, tile == 0);
 }
 
 // One realization: one block per tile, tiles [tile0, tile0 + gridDim.x).
