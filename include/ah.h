@@ -217,7 +217,8 @@ int ah_set_kernel(ah_ctx *ctx, int32_t kernel, int32_t tile_y, int32_t chunk_z);
  * tile, z-chunk) items -- the ensemble form for many independent
  * realizations of uneven size (Sec. 1 and Sec. 5 of the paper motivate
  * thousands of runs); it needs nx % 64 == 0 and one common step0, and falls
- * back to one launch per realization otherwise.  graph_steps = g > 0: runs
+ * back to one launch per realization otherwise.  Where the two-step kernel is
+ * in use, unmeasured pairs are likewise one persistent launch per pair.  graph_steps = g > 0: runs
  * of g unmeasured steps are captured once into a hipGraph (on a stream of
  * the context, ordered after and before the caller's stream with events) and
  * replayed; measuring steps are launched directly.  0, 0 is the default.

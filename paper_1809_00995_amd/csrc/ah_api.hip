@@ -47,10 +47,14 @@ struct ah_ctx {
     std::vector<int> cz2;
     int batched = 0;                  // 1: one persistent launch per step
     int graph_steps = 0;              // > 0: replay runs of unmeasured steps from a graph
-    // batched work list (rebuilt when the configuration changes)
+    // batched work lists (rebuilt when the configuration changes): single-step
+    // tiles and two-step tiles
     BatchItem *d_items = nullptr;
     int n_items = 0, items_ty = 0, grid_step = 0, grid_meas = 0;
     bool items_valid = false;
+    BatchItem *d_items2 = nullptr;
+    int n_items2 = 0, items2_ty = 0, grid2 = 0;
+    bool items2_valid = false;
     // graph replay
     hipStream_t gstream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -155,6 +159,7 @@ bool frozen(const ah_ctx *c, int r) {
 
 void invalidate_plans(ah_ctx *c) {
     c->items_valid = false;
+    c->items2_valid = false;
     if (c->gexec)
         (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
@@ -208,7 +213,7 @@ bool use_tiled(const ah_ctx *c, int r) {
 }
 
 // Unmeasured steps go in pairs through the two-step kernel: explicitly, or by
-// default for FP32 in the 20-plane layout (per-realization launches only).
+// default for FP32 in the 20-plane layout.
 // In FP64 the two-step kernel holds twice the LDS and registers per site and
 // runs slower than single steps, so AUTO keeps single steps there.
 bool use_tiled2(const ah_ctx *c) {
@@ -331,16 +336,65 @@ int build_items(ah_ctx *c) {
     return AH_OK;
 }
 
+// Work list of the batched two-step kernel (same order, two-step tile shape).
+int build_items2(ah_ctx *c) {
+    if (c->items2_valid)
+        return AH_OK;
+    const bool fp64 = c->prec == AH_FP64;
+    int ty = c->tile_y2;
+    {
+        int z = 0;
+        tiled2_defaults(fp64, 64, 64, 64, ty, z);
+    }
+    std::vector<int> order(c->nreal);
+    for (int r = 0; r < c->nreal; ++r)
+        order[r] = r;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return sites_of(c->p[a]) > sites_of(c->p[b]); });
+    std::vector<BatchItem> items;
+    for (int r : order) {
+        const ah_params &q = c->p[r];
+        int t = ty, z = c->cz2[r];
+        tiled2_defaults(fp64, q.nx, q.ny, q.nz, t, z);
+        const int tiles = (q.nx / 64) * ((q.ny + ty - 1) / ty) * ((q.nz + z - 1) / z);
+        for (int k = 0; k < tiles; ++k)
+            items.push_back(BatchItem{ r, k, z, 0 });
+    }
+    if (c->d_items2)
+        (void)hipFree(c->d_items2);
+    c->d_items2 = nullptr;
+    HIP_TRY(c, hipMalloc(&c->d_items2, items.size() * sizeof(BatchItem)));
+    HIP_TRY(c, hipMemcpyAsync(c->d_items2, items.data(), items.size() * sizeof(BatchItem),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int rc = batch2_dispatch(fp64, ty, nullptr, nullptr, nullptr, 0, c->nreal, 0, nullptr,
+                             &c->grid2);
+    if (rc)
+        return fail(c, AH_E_HIP, "occupancy query failed: %s", hipGetErrorString((hipError_t)rc));
+    c->n_items2 = (int)items.size();
+    c->items2_ty = ty;
+    c->items2_valid = true;
+    return AH_OK;
+}
+
 // One pass over memory of every realization: bookkeeping for `steps` (1 or
-// 2) steps, then the kernels.  A one-step pass uses the batched kernel or one
-// launch per realization; slots_row[r] receives the measurement of
-// realization r when want_meas[r] (slots_row == NULL: no measurement).  A
-// two-step pass (never measuring) launches the two-step kernel per
-// realization.  With skip_frozen the host leaves out realizations that
-// reached n_end (the device skips them anyway, which keeps captured graphs
-// valid).
+// 2) steps, then the kernels: the batched kernel of that many steps, or one
+// launch per realization.  slots_row[r] receives the measurement of
+// realization r when want_meas[r] (slots_row == NULL: no measurement;
+// two-step passes never measure).  With skip_frozen the host leaves out
+// realizations that reached n_end (the device skips them anyway, which keeps
+// captured graphs valid).
 int launch_pass(ah_ctx *c, int steps, Slot *slots_row, const char *want_meas, bool skip_frozen) {
     TRY(launch_bookkeep(c, steps));
+    if (steps == 2 && batch_ok(c)) {
+        TRY(build_items2(c));
+        int rc = batch2_dispatch(c->prec == AH_FP64, c->items2_ty, c->d_desc, c->d_coef,
+                                 c->d_items2, c->n_items2, c->nreal, c->grid2, c->stream, nullptr);
+        if (rc)
+            return fail(c, AH_E_HIP, "batched two-step kernel launch failed: %s",
+                        hipGetErrorString((hipError_t)rc));
+        return AH_OK;
+    }
     if (steps == 2) {
         for (int r = 0; r < c->nreal; ++r) {
             if (skip_frozen && frozen(c, r))
@@ -387,10 +441,10 @@ void mirror_pass(ah_ctx *c, int steps) {
 }
 
 // Passes that advance g steps: pairs through the two-step kernel where it is
-// in use (and the launch is not batched), then a single step for an odd one.
+// in use, then a single step for an odd one.
 std::vector<int> pass_plan(const ah_ctx *c, int64_t g) {
     std::vector<int> v;
-    const bool two = use_tiled2(c) && !batch_ok(c);
+    const bool two = use_tiled2(c);
     for (int64_t k = 0; k < g;) {
         const int s = two && g - k >= 2 ? 2 : 1;
         v.push_back(s);
@@ -408,8 +462,11 @@ int run_graph(ah_ctx *c, int64_t reps) {
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
     }
-    if (batch_ok(c))
-        TRY(build_items(c));     // outside the capture: it copies and synchronises
+    if (batch_ok(c)) {
+        TRY(build_items(c));     // outside the capture: they copy and synchronise
+        if (use_tiled2(c))
+            TRY(build_items2(c));
+    }
     const std::vector<int> plan = pass_plan(c, c->graph_steps);
     if (!c->gexec_valid) {
         hipStream_t user = c->stream;
@@ -458,7 +515,7 @@ void release(ah_ctx *c) {
     if (c->gstream)
         (void)hipStreamDestroy(c->gstream);
     void *ptrs[] = { c->d_desc, c->d_step, c->d_copy, c->d_coef, c->d_slots, c->d_obs, c->d_gauss,
-                     c->d_items };
+                     c->d_items, c->d_items2 };
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -628,7 +685,7 @@ int ah_step(ah_ctx *c, int64_t nsteps, int32_t measure_every, ah_obs *out, int64
 
     size_t next = 0;
     int64_t i = 0;
-    const bool two = use_tiled2(c) && !batch_ok(c);
+    const bool two = use_tiled2(c);
     while (i < nsteps) {
         if (next < meas.size() && meas_at[next] == i) {
             // measured states take a single-step pass with the fused measurement
@@ -791,7 +848,7 @@ int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
         return fail(c, AH_E_STATE, "autotuning needs the tiled kernel (nx %% 64 == 0)");
     const bool fp64 = c->prec == AH_FP64;
     // the kernel that runs the unmeasured steps
-    const bool two = use_tiled2(c) && !batch_ok(c);
+    const bool two = use_tiled2(c);
     const int ty_cap = c->batched ? tiled_ty_max(fp64, MODE_STEP_MEASURE) : tiled_ty_max(fp64, MODE_STEP);
     std::vector<int> tys;
     for (int t : { 4, 8, 16 })

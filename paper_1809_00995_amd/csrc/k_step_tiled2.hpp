@@ -424,6 +424,30 @@ k_step_tiled2(const RealDesc *descs, const Coef *coefs, int r, int nreal, int cz
     tiled2_tile<T, TY>(d, c0, c1, xcd_remap(blockIdx.x, gridDim.x), cz);
 }
 
+// Many realizations in one launch (the ensemble form): a persistent grid
+// walks the item list (every realization's tiles in the two-step tile shape)
+// in rounds of gridDim.x items, with the XCD remap within a round.
+// Realizations that reached n_end are skipped; one with a single step left
+// takes one step.
+template <typename T, int TY>
+__global__ void __launch_bounds__(64 * Tile2Geom<TY>::NW)
+k_step_batch2(const RealDesc *descs, const Coef *coefs, const BatchItem *items, int n_items,
+              int nreal) {
+    const int g = gridDim.x;
+    const int b = xcd_remap(blockIdx.x, g);
+    for (int base = 0; base < n_items; base += g) {
+        const int it = base + b;
+        if (it >= n_items)
+            break;
+        const BatchItem item = items[it];
+        const Coef c0 = coefs[item.r];
+        if (!c0.active)
+            continue;
+        const RealDesc d = descs[item.r];
+        tiled2_tile<T, TY>(d, c0, coefs[nreal + item.r], item.tile, item.cz);
+    }
+}
+
 // Tile heights of the two-step kernel (LDS: FP32 94 KB at TY = 8, FP64
 // 120 KB at TY = 4; a workgroup may hold up to 160 KB on gfx950).
 inline bool tiled2_ty_valid(bool fp64, int ty) {
@@ -469,6 +493,51 @@ inline int launch_step_tiled2(bool fp64, const RealDesc *desc, const Coef *coef,
         e = launch_tiled2_ty<float, 4>(desc, coef, r, nreal, nx, ny, nz, cz, stream);
     else
         e = launch_tiled2_ty<float, 8>(desc, coef, r, nreal, nx, ny, nz, cz, stream);
+    return (int)e;
+}
+
+} // namespace ah
+
+namespace ah {
+
+template <typename T, int TY>
+hipError_t batch2_ty(const RealDesc *desc, const Coef *coef, const BatchItem *items, int n_items,
+                     int nreal, int grid, hipStream_t stream, int *grid_out) {
+    if (grid_out) {
+        int per_cu = 0, dev = 0, cus = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_batch2<T, TY>,
+                                                             64 * Tile2Geom<TY>::NW, 0);
+        *grid_out = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+        return e;
+    }
+    if (grid > n_items)
+        grid = n_items;
+    if (grid < 1)
+        return hipSuccess;
+    hipLaunchKernelGGL((k_step_batch2<T, TY>), dim3((unsigned)grid), dim3(64 * Tile2Geom<TY>::NW),
+                       0, stream, desc, coef, items, n_items, nreal);
+    return hipGetLastError();
+}
+
+// The batched two-step kernel: with grid_out != NULL only its resident-block
+// count (occupancy x compute units) is returned; otherwise it is launched on
+// `grid` blocks.
+inline int batch2_dispatch(bool fp64, int ty, const RealDesc *desc, const Coef *coef,
+                           const BatchItem *items, int n_items, int nreal, int grid,
+                           hipStream_t stream, int *grid_out) {
+    if (!tiled2_ty_valid(fp64, ty))
+        return (int)hipErrorInvalidValue;
+    hipError_t e;
+    if (fp64)
+        e = batch2_ty<double, 4>(desc, coef, items, n_items, nreal, grid, stream, grid_out);
+    else if (ty == 4)
+        e = batch2_ty<float, 4>(desc, coef, items, n_items, nreal, grid, stream, grid_out);
+    else
+        e = batch2_ty<float, 8>(desc, coef, items, n_items, nreal, grid, stream, grid_out);
     return (int)e;
 }
 

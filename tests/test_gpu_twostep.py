@@ -182,3 +182,38 @@ def test_two_step_autotune_keeps_results():
     with AH.Context([q], [AH.alloc_planes(q)]) as c:
         c.step(11)
         assert torch.equal(c.fields(), tuned)
+
+
+@pytest.mark.parametrize("prec", [AH.AH_FP32, AH.AH_FP64])
+def test_two_step_batched_ensemble(prec):
+    """The ensemble form with two-step passes: one persistent launch per pair
+    (eager and replayed from graphs) over realizations of uneven size, one
+    stopping at an odd n_end, equals single steps launched per realization."""
+    _print_case(test="two_step_batched", prec=prec)
+    ps = [AH.Params(64, 8, 8, precision=prec, tau_ref=2.0, era_p=1.0, s=1.0, seed=71),
+          AH.Params(128, 16, 12, precision=prec, tau_ref=3.0, era_p=2.0, s=0.0, seed=72),
+          AH.Params(64, 24, 20, precision=prec, tau_ref=2.5, era_p=1.0, s=0.0, seed=73, n_end=9),
+          AH.Params(192, 6, 5, precision=prec, tau_ref=1.5, era_p=2.0, s=0.0, seed=74)]
+
+    def run(layout, kernel, batched, graph_steps):
+        qs = [AH.Params(**{**p.__dict__, "layout": layout}) for p in ps]
+        with AH.Context(qs, [AH.alloc_planes(q) for q in qs]) as c:
+            c.set_kernel(kernel)
+            c.set_launch(batched, graph_steps)
+            obs = c.step(17, measure_every=5)
+            return ([c.fields(r).clone() for r in range(len(qs))], obs,
+                    [c.current_step(r) for r in range(len(qs))])
+
+    ref_f, ref_o, ref_s = run(L15, AH.AH_KERNEL_TILED, False, 0)
+    assert ref_s == [17, 17, 9, 17]
+    for g in (0, 3, 4):
+        f, o, s = run(L20, AH.AH_KERNEL_TILED2, True, g)
+        assert s == ref_s
+        for r in range(len(ps)):
+            assert torch.equal(f[r], ref_f[r]), (g, r)
+        assert len(o) == len(ref_o)
+        for row, ref_row in zip(o, ref_o):
+            for a, b in zip(row, ref_row):
+                assert a.step == b.step and a.n_wind_dir == b.n_wind_dir
+                if a.step >= 0:
+                    assert a.energy == pytest.approx(b.energy, rel=1e-12)
