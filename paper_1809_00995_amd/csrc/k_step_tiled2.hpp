@@ -88,16 +88,52 @@ template <typename T> struct Below {
     T pr, pm, uzc, uzs, pyz, pzx;
 };
 
-// Gather the stencil of the site at LDS index q of a state staged with row
-// width W: buffer C holds plane z, buffer N plane z+1.  own/up are the site's
-// values at z and z+1 (registers), bel its carried values from z-1, and
-// pi_e its momenta at z.
+// The three forward plaquette sines based at site s (Eq. (3)): xy, yz, zx at
+// s, from its phasors on plane z (own) and z+1 (up) and those of s+x, s+y on
+// plane z (buffer C, row width W).  The argument order is the single-step
+// kernel's, so the values are bitwise the same whichever thread forms them.
+template <typename T> struct Plaq3 {
+    T xy, yz, zx;
+};
+
 template <typename T, int W, int S>
-__device__ __forceinline__ Stencil<T> gather(const T (*C)[S], const T (*N)[S], int q,
+__device__ __forceinline__ Plaq3<T> fwd_plaquettes(const T (*C)[S], int q, const Phasors<T> &own,
+                                                   const Phasors<T> &up) {
+    Plaq3<T> p;
+    p.xy = plaq_sin(own.uxc, own.uxs, C[Q_UYC][q + 1], C[Q_UYS][q + 1], C[Q_UXC][q + W],
+                    C[Q_UXS][q + W], own.uyc, own.uys);
+    p.yz = plaq_sin(own.uyc, own.uys, C[Q_UZC][q + W], C[Q_UZS][q + W], up.uyc, up.uys, own.uzc,
+                    own.uzs);
+    p.zx = plaq_sin(own.uzc, own.uzs, up.uxc, up.uxs, C[Q_UZC][q + 1], C[Q_UZS][q + 1], own.uxc,
+                    own.uxs);
+    return p;
+}
+
+template <typename T, int S>
+__device__ __forceinline__ Phasors<T> get_phasors(const T (*C)[S], int k) {
+    Phasors<T> v;
+    v.pr = C[Q_PR][k];
+    v.pm = C[Q_PI][k];
+    v.uxc = C[Q_UXC][k];
+    v.uxs = C[Q_UXS][k];
+    v.uyc = C[Q_UYC][k];
+    v.uys = C[Q_UYS][k];
+    v.uzc = C[Q_UZC][k];
+    v.uzs = C[Q_UZS][k];
+    return v;
+}
+
+// Gather the stencil of the site at LDS index q of a state staged with row
+// width W on plane z (buffer C).  own/up are the site's values at z and z+1
+// (registers), bel its carried values from z-1, pi_e its momenta at z, fp its
+// forward plaquettes, and P the forward plaquettes of every site of plane z
+// (those of x-x and x-y are read).
+template <typename T, int W, int S>
+__device__ __forceinline__ Stencil<T> gather(const T (*C)[S], const T (*P)[S], int q,
                                              const Phasors<T> &own, T ax, T ay, T az,
                                              const Phasors<T> &up, const Below<T> &bel,
                                              T pr0, T pi0, T ex0, T ey0, T ez0,
-                                             T &pyz_out, T &pzx_out) {
+                                             const Plaq3<T> &fp) {
     Stencil<T> st;
     st.pr = own.pr; st.pm = own.pm; st.ax = ax; st.ay = ay; st.az = az;
     st.uxc = own.uxc; st.uxs = own.uxs; st.uyc = own.uyc; st.uys = own.uys;
@@ -108,34 +144,18 @@ __device__ __forceinline__ Stencil<T> gather(const T (*C)[S], const T (*N)[S], i
     st.pr_yp = C[Q_PR][q + W]; st.pi_yp = C[Q_PI][q + W];
     st.pr_ym = C[Q_PR][q - W]; st.pi_ym = C[Q_PI][q - W];
     st.pr_zp = up.pr; st.pi_zp = up.pm; st.pr_zm = bel.pr; st.pi_zm = bel.pm;
-    const T uxc_xm = C[Q_UXC][q - 1], uxs_xm = C[Q_UXS][q - 1];
-    const T uxc_yp = C[Q_UXC][q + W], uxs_yp = C[Q_UXS][q + W];
-    const T uxc_xmyp = C[Q_UXC][q - 1 + W], uxs_xmyp = C[Q_UXS][q - 1 + W];
-    const T uxc_ym = C[Q_UXC][q - W], uxs_ym = C[Q_UXS][q - W];
-    const T uyc_xp = C[Q_UYC][q + 1], uys_xp = C[Q_UYS][q + 1];
-    const T uyc_ym = C[Q_UYC][q - W], uys_ym = C[Q_UYS][q - W];
-    const T uyc_xm = C[Q_UYC][q - 1], uys_xm = C[Q_UYS][q - 1];
-    const T uyc_xpym = C[Q_UYC][q + 1 - W], uys_xpym = C[Q_UYS][q + 1 - W];
-    const T uzc_xp = C[Q_UZC][q + 1], uzs_xp = C[Q_UZS][q + 1];
-    const T uzc_yp = C[Q_UZC][q + W], uzs_yp = C[Q_UZS][q + W];
-    const T uzc_xm = C[Q_UZC][q - 1], uzs_xm = C[Q_UZS][q - 1];
-    const T uzc_ym = C[Q_UZC][q - W], uzs_ym = C[Q_UZS][q - W];
-    const T uxc_xmzp = N[Q_UXC][q - 1], uxs_xmzp = N[Q_UXS][q - 1];
-    const T uyc_ymzp = N[Q_UYC][q - W], uys_ymzp = N[Q_UYS][q - W];
-    st.uxc_xm = uxc_xm; st.uxs_xm = uxs_xm; st.uyc_ym = uyc_ym; st.uys_ym = uys_ym;
+    st.uxc_xm = C[Q_UXC][q - 1]; st.uxs_xm = C[Q_UXS][q - 1];
+    st.uyc_ym = C[Q_UYC][q - W]; st.uys_ym = C[Q_UYS][q - W];
     st.uzc_zm = bel.uzc; st.uzs_zm = bel.uzs;
-    // plaquette sines (Eq. (3)), same argument order as the single-step kernel
-    st.pxy = plaq_sin(own.uxc, own.uxs, uyc_xp, uys_xp, uxc_yp, uxs_yp, own.uyc, own.uys);
-    st.pxy_xm = plaq_sin(uxc_xm, uxs_xm, own.uyc, own.uys, uxc_xmyp, uxs_xmyp, uyc_xm, uys_xm);
-    st.pxy_ym = plaq_sin(uxc_ym, uxs_ym, uyc_xpym, uys_xpym, own.uxc, own.uxs, uyc_ym, uys_ym);
-    st.pyz = plaq_sin(own.uyc, own.uys, uzc_yp, uzs_yp, up.uyc, up.uys, own.uzc, own.uzs);
-    st.pyz_ym = plaq_sin(uyc_ym, uys_ym, own.uzc, own.uzs, uyc_ymzp, uys_ymzp, uzc_ym, uzs_ym);
-    st.pzx = plaq_sin(own.uzc, own.uzs, up.uxc, up.uxs, uzc_xp, uzs_xp, own.uxc, own.uxs);
-    st.pzx_xm = plaq_sin(uzc_xm, uzs_xm, uxc_xmzp, uxs_xmzp, own.uzc, own.uzs, uxc_xm, uxs_xm);
+    st.pxy = fp.xy;
+    st.pyz = fp.yz;
+    st.pzx = fp.zx;
+    st.pxy_xm = P[0][q - 1];
+    st.pzx_xm = P[2][q - 1];
+    st.pxy_ym = P[0][q - W];
+    st.pyz_ym = P[1][q - W];
     st.pyz_zm = bel.pyz;
     st.pzx_zm = bel.pzx;
-    pyz_out = st.pyz;
-    pzx_out = st.pzx;
     return st;
 }
 
@@ -183,6 +203,8 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
     using G = Tile2Geom<TY>;
     __shared__ T sa[2][Q_COUNT][G::S2];   // S_n on R2, planes z and z+1
     __shared__ T sb[2][Q_COUNT][G::S1];   // S_{n+1} on R1, two planes
+    __shared__ T pa[3][G::S2];            // forward plaquettes of S_n, plane of step one
+    __shared__ T pb[3][G::S1];            // forward plaquettes of S_{n+1}, plane of step two
 
     const int nx = d.nx, ny = d.ny, nz = d.nz;
     const int ntx = nx >> 6, nty = (ny + TY - 1) / TY;
@@ -214,6 +236,11 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
         G::ring2(h2, rx, ry);
     const int rq = G::i2(rx, ry);
     const int rgx = wrap_mod(x0 + rx, nx), rgy = wrap_mod(y0 + ry, ny);
+    // forward plaquettes that step one reads at x-x and x-y of the R1 ring
+    const bool edge2 = stager && ((rx == -2 && ry >= -1 && ry <= TY) || (ry == -2 && rx >= -1 && rx <= 64));
+    // forward plaquettes of S_{n+1} that step two needs: the tile and the
+    // ring's column x = -1 and row y = -1 next to it
+    const bool need1 = inner || (lx == -1 && ly >= 0 && ly < TY) || (ly == -1 && lx >= 0 && lx < 64);
 
     const int par = c0.parity, L = d.layout;
     gptr<const T> in[10];
@@ -253,9 +280,9 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
     Below<T> bel;
     {
         const Raw rb = load_raw(own_site(za));
-        const Phasors<T> pb = make_phasors(rb.pr, rb.pm, rb.ax, rb.ay, rb.az);
+        const Phasors<T> pbel = make_phasors(rb.pr, rb.pm, rb.ax, rb.ay, rb.az);
         if (has1)
-            put_phasors<T, G::S2>(sa[1], q2, pb);
+            put_phasors<T, G::S2>(sa[1], q2, pbel);
         stage_ring(1, za);
         rcur = load_raw(own_site(zb));
         pcur = make_phasors(rcur.pr, rcur.pm, rcur.ax, rcur.ay, rcur.az);
@@ -265,11 +292,11 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
         lds_barrier();
         bel.pyz = bel.pzx = 0;
         if (has1)
-            base_plaquettes<T, G::W2, G::S2>(sa[1], q2, pb, pcur, bel.pyz, bel.pzx);
-        bel.pr = pb.pr;
-        bel.pm = pb.pm;
-        bel.uzc = pb.uzc;
-        bel.uzs = pb.uzs;
+            base_plaquettes<T, G::W2, G::S2>(sa[1], q2, pbel, pcur, bel.pyz, bel.pzx);
+        bel.pr = pbel.pr;
+        bel.pm = pbel.pm;
+        bel.uzc = pbel.uzc;
+        bel.uzs = pbel.uzs;
         lds_barrier();
     }
 
@@ -333,34 +360,57 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
         const int zs = zwrap(z0 - 1 + k);
         // (a) stage S_n at zs+1 from the prefetched values; start the next reads
         const T pr0 = f_pr0, pi0 = f_pi0, ex0 = f_ex0, ey0 = f_ey0, ez0 = f_ez0;
+        // and form the forward plaquettes of plane zs (complete since the last
+        // barrier) for the own site and the outer ring's column and row that
+        // step one reads
         nxt.r = f_own;
+        Plaq3<T> fp{};
         if (has1) {
             nxt.p = make_phasors(nxt.r.pr, nxt.r.pm, nxt.r.ax, nxt.r.ay, nxt.r.az);
             put_phasors<T, G::S2>(sa[NB], q2, nxt.p);
+            fp = fwd_plaquettes<T, G::W2, G::S2>(sa[CB], q2, cur.p, nxt.p);
+            pa[0][q2] = fp.xy;
+            pa[1][q2] = fp.yz;
+            pa[2][q2] = fp.zx;
         }
-        if (stager)
-            put_phasors<T, G::S2>(sa[NB], rq, make_phasors(f_ring.pr, f_ring.pm, f_ring.ax,
-                                                           f_ring.ay, f_ring.az));
+        if (stager) {
+            const Phasors<T> up = make_phasors(f_ring.pr, f_ring.pm, f_ring.ax, f_ring.ay, f_ring.az);
+            put_phasors<T, G::S2>(sa[NB], rq, up);
+            if (edge2) {
+                const Plaq3<T> rp =
+                    fwd_plaquettes<T, G::W2, G::S2>(sa[CB], rq, get_phasors<T, G::S2>(sa[CB], rq), up);
+                pa[0][rq] = rp.xy;
+                pa[1][rq] = rp.yz;
+                pa[2][rq] = rp.zx;
+            }
+        }
         if (k + 1 < nk)
             prefetch(k + 1);
         lds_barrier();
 
-        // (b) step one at (own R1 site, zs)
+        // (b) step one at (own R1 site, zs); then the forward plaquettes of
+        // S_{n+1} at zs-1, which need the own site's S_{n+1} at zs just formed
+        Plaq3<T> fp1{};
         if (has1) {
-            T pyz, pzx;
-            const Stencil<T> st = gather<T, G::W2, G::S2>(sa[CB], sa[NB], q2, cur.p, cur.r.ax,
+            const Stencil<T> st = gather<T, G::W2, G::S2>(sa[CB], pa, q2, cur.p, cur.r.ax,
                                                           cur.r.ay, cur.r.az, nxt.p, bel, pr0,
-                                                          pi0, ex0, ey0, ez0, pyz, pzx);
+                                                          pi0, ex0, ey0, ez0, fp);
             n1.v = leapfrog_site(st, K0);
             bel.pr = cur.p.pr;
             bel.pm = cur.p.pm;
             bel.uzc = cur.p.uzc;
             bel.uzs = cur.p.uzs;
-            bel.pyz = pyz;
-            bel.pzx = pzx;
+            bel.pyz = fp.yz;
+            bel.pzx = fp.zx;
             if (two) {
                 n1.p = make_phasors(n1.v.qr, n1.v.qi, n1.v.ax, n1.v.ay, n1.v.az);
                 put_phasors<T, G::S1>(sb[CB], q1, n1.p);
+                if (need1 && k >= 1) {
+                    fp1 = fwd_plaquettes<T, G::W1, G::S1>(sb[NB], q1, c1.p, n1.p);
+                    pb[0][q1] = fp1.xy;
+                    pb[1][q1] = fp1.yz;
+                    pb[2][q1] = fp1.zx;
+                }
             }
         }
         if (!two) {
@@ -374,28 +424,23 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
 
         // (c) step two at (tile site, zs - 1), one plane behind
         if (inner) {
-            if (k == 1) {
-                // carried values of plane z0-1 for the first plane of step two
-                base_plaquettes<T, G::W1, G::S1>(sb[NB], q1, c1.p, n1.p, bel1.pyz, bel1.pzx);
-                bel1.pr = c1.p.pr;
-                bel1.pm = c1.p.pm;
-                bel1.uzc = c1.p.uzc;
-                bel1.uzs = c1.p.uzs;
-            } else if (k >= 2) {
-                T pyz, pzx;
-                const Stencil<T> st = gather<T, G::W1, G::S1>(sb[NB], sb[CB], q1, c1.p, c1.v.ax,
+            if (k >= 2) {
+                const Stencil<T> st = gather<T, G::W1, G::S1>(sb[NB], pb, q1, c1.p, c1.v.ax,
                                                               c1.v.ay, c1.v.az, n1.p, bel1,
                                                               c1.v.pr, c1.v.pi, c1.v.ex,
-                                                              c1.v.ey, c1.v.ez, pyz, pzx);
+                                                              c1.v.ey, c1.v.ez, fp1);
                 const SiteNew<T> n2 = leapfrog_site(st, K1);
                 if (owner)
                     store_state(n2, own_site(zwrap(zs - 1)));
+            }
+            if (k >= 1) {
+                // plane zs-1 is below the next plane of step two
                 bel1.pr = c1.p.pr;
                 bel1.pm = c1.p.pm;
                 bel1.uzc = c1.p.uzc;
                 bel1.uzs = c1.p.uzs;
-                bel1.pyz = pyz;
-                bel1.pzx = pzx;
+                bel1.pyz = fp1.yz;
+                bel1.pzx = fp1.zx;
             }
         }
     };
