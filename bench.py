@@ -60,10 +60,8 @@ def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15):
     p = AH.Params(n, n, n, precision=prec, dx=0.5, dt=0.1, tau0=0.0, tau_ref=n * 0.5 / 2.0,
                   era_p=2.0, s=0.0, seed=2024,
                   layout=AH.AH_LAYOUT_20 if layout == 20 else AH.AH_LAYOUT_15)
-    # the library's choice: pairs through the two-step kernel in the 20-plane
-    # layout (by default for FP32 only)
-    two = layout == 20 and (kernel == AH.AH_KERNEL_TILED2 or
-                            (kernel == AH.AH_KERNEL_AUTO and prec == AH.AH_FP32))
+    # the library's choice: pairs through the two-step kernel in the 20-plane layout
+    two = layout == 20 and kernel in (AH.AH_KERNEL_TILED2, AH.AH_KERNEL_AUTO)
     planes = AH.alloc_planes(p)
     ctx = AH.Context([p], [planes])
     if kernel != AH.AH_KERNEL_AUTO:
@@ -111,10 +109,7 @@ def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15):
 # (FETCH_SIZE x 2 + WRITE_SIZE x 1, factors from a 1 GiB device copy measured
 # in the same runs), for the kernel as it was profiled; the summaries and
 # commands are in profiles/.  Keyed by (dtype, layout, kernel option, lattice).
-PROFILED_TRAFFIC_BYTES = {
-    # k_step_tiled2<float, 8> with LDS-shared plaquettes, profiles/step_tiled2_512cubed.md
-    ("f32", 20, "auto", 512): 12.07e9,
-}
+PROFILED_TRAFFIC_BYTES = {}
 
 
 def profiled_traffic(dt, layout, kernel, n):

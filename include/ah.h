@@ -65,7 +65,7 @@ enum {
 
 enum {
     AH_KERNEL_AUTO = 0,       /* the library's fastest variant for the shape, precision and
-                                 layout (AH_KERNEL_TILED2 for FP32 with AH_LAYOUT_20)       */
+                                 layout (AH_KERNEL_TILED2 with AH_LAYOUT_20)                */
     AH_KERNEL_PLAIN = 1,      /* one thread per site, every neighbour read from memory     */
     AH_KERNEL_TILED = 2,      /* z-streaming tiles with LDS-staged phasors and plaquettes  */
     AH_KERNEL_TILED2 = 3      /* two steps per pass over memory: each block advances its

@@ -54,7 +54,7 @@ struct ah_ctx {
     bool items_valid = false;
     BatchItem *d_items2 = nullptr;
     int n_items2 = 0, items2_ty = 0, grid2 = 0;
-    bool items2_valid = false;
+    bool items2_off32 = false, items2_valid = false;
     // graph replay
     hipStream_t gstream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -213,13 +213,11 @@ bool use_tiled(const ah_ctx *c, int r) {
 }
 
 // Unmeasured steps go in pairs through the two-step kernel: explicitly, or by
-// default for FP32 in the 20-plane layout.
-// In FP64 the two-step kernel holds twice the LDS and registers per site and
-// runs slower than single steps, so AUTO keeps single steps there.
+// default in the 20-plane layout.
 bool use_tiled2(const ah_ctx *c) {
     if (c->layout != AH_LAYOUT_20 || !tiled_ok(c))
         return false;
-    return c->kernel == AH_KERNEL_TILED2 || (c->kernel == AH_KERNEL_AUTO && c->prec == AH_FP32);
+    return c->kernel == AH_KERNEL_TILED2 || c->kernel == AH_KERNEL_AUTO;
 }
 
 // The batched kernel needs tiled shapes and one common step index (so every
@@ -367,12 +365,16 @@ int build_items2(ah_ctx *c) {
     HIP_TRY(c, hipMemcpyAsync(c->d_items2, items.data(), items.size() * sizeof(BatchItem),
                               hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    int rc = batch2_dispatch(fp64, ty, nullptr, nullptr, nullptr, 0, c->nreal, 0, nullptr,
+    bool off32 = true;
+    for (const auto &q : c->p)
+        off32 = off32 && fits_off32(sites_of(q), fp64 ? 8 : 4);
+    int rc = batch2_dispatch(fp64, ty, off32, nullptr, nullptr, nullptr, 0, c->nreal, 0, nullptr,
                              &c->grid2);
     if (rc)
         return fail(c, AH_E_HIP, "occupancy query failed: %s", hipGetErrorString((hipError_t)rc));
     c->n_items2 = (int)items.size();
     c->items2_ty = ty;
+    c->items2_off32 = off32;
     c->items2_valid = true;
     return AH_OK;
 }
@@ -388,8 +390,9 @@ int launch_pass(ah_ctx *c, int steps, Slot *slots_row, const char *want_meas, bo
     TRY(launch_bookkeep(c, steps));
     if (steps == 2 && batch_ok(c)) {
         TRY(build_items2(c));
-        int rc = batch2_dispatch(c->prec == AH_FP64, c->items2_ty, c->d_desc, c->d_coef,
-                                 c->d_items2, c->n_items2, c->nreal, c->grid2, c->stream, nullptr);
+        int rc = batch2_dispatch(c->prec == AH_FP64, c->items2_ty, c->items2_off32, c->d_desc,
+                                 c->d_coef, c->d_items2, c->n_items2, c->nreal, c->grid2,
+                                 c->stream, nullptr);
         if (rc)
             return fail(c, AH_E_HIP, "batched two-step kernel launch failed: %s",
                         hipGetErrorString((hipError_t)rc));

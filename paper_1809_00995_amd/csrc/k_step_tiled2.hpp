@@ -196,8 +196,11 @@ __device__ __forceinline__ Phasors<T> make_phasors(T pr, T pm, T ax, T ay, T az)
 
 // One tile (64 x TY sites, planes [z0, z0 + cz)) of one realization: S_n in
 // copy c0.parity -> S_{n+2} (or S_{n+1} when c1 is not active) in the other
-// copy.  Every thread of the block calls it with the same arguments.
-template <typename T, int TY>
+// copy.  OFF32: every plane is below 4 GiB, so element addresses are one
+// 32-bit byte offset shared by all planes from each plane's base (scalar
+// registers); otherwise 64-bit addresses.  Every thread of the block calls it
+// with the same arguments.
+template <typename T, int TY, bool OFF32>
 __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, const Coef &c1,
                                             int tile, int cz) {
     using G = Tile2Geom<TY>;
@@ -253,17 +256,31 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
 
     auto own_site = [&](int z) { return gx + nx * (gy + ny * z); };
     auto zwrap = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
+    // element s of field f of S_n, and the store of the new state
+    auto LD = [&](int f, int s) -> T {
+        if constexpr (OFF32)
+            return *(gptr<const T>)((gptr<const char>)in[f] + (uint32_t)s * (uint32_t)sizeof(T));
+        else
+            return in[f][s];
+    };
+    auto ST = [&](int f, int s, T v) {
+        if constexpr (OFF32)
+            __builtin_nontemporal_store(
+                v, (gptr<T>)((gptr<char>)out[f] + (uint32_t)s * (uint32_t)sizeof(T)));
+        else
+            __builtin_nontemporal_store(v, out[f] + s);
+    };
     // S_n at (own site, z): phi, A and phasors
     struct Raw {
         T pr, pm, ax, ay, az;
     };
     auto load_raw = [&](int s) {
         Raw r;
-        r.pr = in[0][s];
-        r.pm = in[1][s];
-        r.ax = in[4][s];
-        r.ay = in[5][s];
-        r.az = in[6][s];
+        r.pr = LD(0, s);
+        r.pm = LD(1, s);
+        r.ax = LD(4, s);
+        r.ay = LD(5, s);
+        r.az = LD(6, s);
         return r;
     };
     auto stage_ring = [&](int bf, int z) {
@@ -309,27 +326,27 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
         const int zs = zwrap(z0 - 1 + k), zn = zwrap(z0 + k);
         if (has1) {
             const int s = own_site(zs);
-            f_pr0 = in[2][s];
-            f_pi0 = in[3][s];
-            f_ex0 = in[7][s];
-            f_ey0 = in[8][s];
-            f_ez0 = in[9][s];
+            f_pr0 = LD(2, s);
+            f_pi0 = LD(3, s);
+            f_ex0 = LD(7, s);
+            f_ey0 = LD(8, s);
+            f_ez0 = LD(9, s);
             f_own = load_raw(own_site(zn));
         }
         if (stager)
             f_ring = load_raw(rgx + nx * (rgy + ny * zn));
     };
     auto store_state = [&](const SiteNew<T> &v, int s) {
-        __builtin_nontemporal_store(v.pr, out[2] + s);
-        __builtin_nontemporal_store(v.pi, out[3] + s);
-        __builtin_nontemporal_store(v.ex, out[7] + s);
-        __builtin_nontemporal_store(v.ey, out[8] + s);
-        __builtin_nontemporal_store(v.ez, out[9] + s);
-        __builtin_nontemporal_store(v.qr, out[0] + s);
-        __builtin_nontemporal_store(v.qi, out[1] + s);
-        __builtin_nontemporal_store(v.ax, out[4] + s);
-        __builtin_nontemporal_store(v.ay, out[5] + s);
-        __builtin_nontemporal_store(v.az, out[6] + s);
+        ST(2, s, v.pr);
+        ST(3, s, v.pi);
+        ST(7, s, v.ex);
+        ST(8, s, v.ey);
+        ST(9, s, v.ez);
+        ST(0, s, v.qr);
+        ST(1, s, v.qi);
+        ST(4, s, v.ax);
+        ST(5, s, v.ay);
+        ST(6, s, v.az);
     };
 
     // Own-site values of one plane: S_n (raw fields and phasors) and S_{n+1}
@@ -458,7 +475,7 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
 
 // One realization: one block per tile.  coefs[r] describes step n,
 // coefs[nreal + r] step n+1.
-template <typename T, int TY>
+template <typename T, int TY, bool OFF32>
 __global__ void __launch_bounds__(64 * Tile2Geom<TY>::NW)
 k_step_tiled2(const RealDesc *descs, const Coef *coefs, int r, int nreal, int cz) {
     const RealDesc d = descs[r];
@@ -466,7 +483,7 @@ k_step_tiled2(const RealDesc *descs, const Coef *coefs, int r, int nreal, int cz
     if (!c0.active)
         return;
     const Coef c1 = coefs[nreal + r];
-    tiled2_tile<T, TY>(d, c0, c1, xcd_remap(blockIdx.x, gridDim.x), cz);
+    tiled2_tile<T, TY, OFF32>(d, c0, c1, xcd_remap(blockIdx.x, gridDim.x), cz);
 }
 
 // Many realizations in one launch (the ensemble form): a persistent grid
@@ -474,7 +491,7 @@ k_step_tiled2(const RealDesc *descs, const Coef *coefs, int r, int nreal, int cz
 // in rounds of gridDim.x items, with the XCD remap within a round.
 // Realizations that reached n_end are skipped; one with a single step left
 // takes one step.
-template <typename T, int TY>
+template <typename T, int TY, bool OFF32>
 __global__ void __launch_bounds__(64 * Tile2Geom<TY>::NW)
 k_step_batch2(const RealDesc *descs, const Coef *coefs, const BatchItem *items, int n_items,
               int nreal) {
@@ -489,7 +506,7 @@ k_step_batch2(const RealDesc *descs, const Coef *coefs, const BatchItem *items, 
         if (!c0.active)
             continue;
         const RealDesc d = descs[item.r];
-        tiled2_tile<T, TY>(d, c0, coefs[nreal + item.r], item.tile, item.cz);
+        tiled2_tile<T, TY, OFF32>(d, c0, coefs[nreal + item.r], item.tile, item.cz);
     }
 }
 
@@ -515,12 +532,22 @@ inline void tiled2_defaults(bool fp64, int nx, int ny, int nz, int &ty, int &cz)
     }
 }
 
+// Whether every plane of an nx*ny*nz lattice of elem-byte values is below
+// 4 GiB (32-bit byte offsets).
+inline bool fits_off32(long n_sites, int elem) {
+    return (unsigned long long)n_sites * (unsigned long long)elem <= (1ull << 32);
+}
+
 template <typename T, int TY>
 hipError_t launch_tiled2_ty(const RealDesc *desc, const Coef *coef, int r, int nreal, int nx, int ny,
                             int nz, int cz, hipStream_t stream) {
     const long blocks = (long)(nx / 64) * ((ny + TY - 1) / TY) * ((nz + cz - 1) / cz);
-    hipLaunchKernelGGL((k_step_tiled2<T, TY>), dim3((unsigned)blocks), dim3(64 * Tile2Geom<TY>::NW),
-                       0, stream, desc, coef, r, nreal, cz);
+    if (fits_off32((long)nx * ny * nz, sizeof(T)))
+        hipLaunchKernelGGL((k_step_tiled2<T, TY, true>), dim3((unsigned)blocks),
+                           dim3(64 * Tile2Geom<TY>::NW), 0, stream, desc, coef, r, nreal, cz);
+    else
+        hipLaunchKernelGGL((k_step_tiled2<T, TY, false>), dim3((unsigned)blocks),
+                           dim3(64 * Tile2Geom<TY>::NW), 0, stream, desc, coef, r, nreal, cz);
     return hipGetLastError();
 }
 
@@ -545,7 +572,7 @@ inline int launch_step_tiled2(bool fp64, const RealDesc *desc, const Coef *coef,
 
 namespace ah {
 
-template <typename T, int TY>
+template <typename T, int TY, bool OFF32>
 hipError_t batch2_ty(const RealDesc *desc, const Coef *coef, const BatchItem *items, int n_items,
                      int nreal, int grid, hipStream_t stream, int *grid_out) {
     if (grid_out) {
@@ -554,7 +581,7 @@ hipError_t batch2_ty(const RealDesc *desc, const Coef *coef, const BatchItem *it
         if (e == hipSuccess)
             e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_batch2<T, TY>,
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_batch2<T, TY, OFF32>,
                                                              64 * Tile2Geom<TY>::NW, 0);
         *grid_out = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
         return e;
@@ -563,26 +590,30 @@ hipError_t batch2_ty(const RealDesc *desc, const Coef *coef, const BatchItem *it
         grid = n_items;
     if (grid < 1)
         return hipSuccess;
-    hipLaunchKernelGGL((k_step_batch2<T, TY>), dim3((unsigned)grid), dim3(64 * Tile2Geom<TY>::NW),
-                       0, stream, desc, coef, items, n_items, nreal);
+    hipLaunchKernelGGL((k_step_batch2<T, TY, OFF32>), dim3((unsigned)grid),
+                       dim3(64 * Tile2Geom<TY>::NW), 0, stream, desc, coef, items, n_items, nreal);
     return hipGetLastError();
 }
 
 // The batched two-step kernel: with grid_out != NULL only its resident-block
 // count (occupancy x compute units) is returned; otherwise it is launched on
-// `grid` blocks.
-inline int batch2_dispatch(bool fp64, int ty, const RealDesc *desc, const Coef *coef,
+// `grid` blocks.  off32: every realization's planes are below 4 GiB.
+inline int batch2_dispatch(bool fp64, int ty, bool off32, const RealDesc *desc, const Coef *coef,
                            const BatchItem *items, int n_items, int nreal, int grid,
                            hipStream_t stream, int *grid_out) {
     if (!tiled2_ty_valid(fp64, ty))
         return (int)hipErrorInvalidValue;
+#define AH_B2(T, TY_)                                                                              \
+    (off32 ? batch2_ty<T, TY_, true>(desc, coef, items, n_items, nreal, grid, stream, grid_out)    \
+           : batch2_ty<T, TY_, false>(desc, coef, items, n_items, nreal, grid, stream, grid_out))
     hipError_t e;
     if (fp64)
-        e = batch2_ty<double, 4>(desc, coef, items, n_items, nreal, grid, stream, grid_out);
+        e = AH_B2(double, 4);
     else if (ty == 4)
-        e = batch2_ty<float, 4>(desc, coef, items, n_items, nreal, grid, stream, grid_out);
+        e = AH_B2(float, 4);
     else
-        e = batch2_ty<float, 8>(desc, coef, items, n_items, nreal, grid, stream, grid_out);
+        e = AH_B2(float, 8);
+#undef AH_B2
     return (int)e;
 }
 

@@ -89,6 +89,25 @@ def test_512cubed_two_step_pass_equals_single_steps(prec):
         assert a.energy == pytest.approx(b.energy, rel=1e-12)
 
 
+def test_planes_above_4gib_two_step_pass():
+    """Planes above 4 GiB (FP64, 1024 x 1024 x 520: 4.36 GB per plane) take the two-step
+    kernel's 64-bit addressing: three steps (a pair and a single step) equal single steps
+    in the 15-plane layout bit for bit."""
+    print("CASE test=large_planes", flush=True)
+    base = dict(precision=AH.AH_FP64, dx=0.5, dt=0.1, tau0=1.0, tau_ref=256.0, era_p=1.0,
+                s=1.0, seed=77)
+    runs = []
+    for layout in (AH.AH_LAYOUT_15, AH.AH_LAYOUT_20):
+        p = AH.Params(1024, 1024, 520, layout=layout, **base)
+        planes = AH.alloc_planes(p)
+        with AH.Context([p], [planes]) as c:
+            c.step(3)
+            runs.append(c.fields().clone())
+        del planes
+        torch.cuda.empty_cache()
+    assert torch.equal(runs[0], runs[1])
+
+
 def test_config_256cubed_radiation_run(O):
     n, steps, every = 256, 640, 10
     print("CASE test=config_256", flush=True)
