@@ -109,7 +109,10 @@ def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15):
 # (FETCH_SIZE x 2 + WRITE_SIZE x 1, factors from a 1 GiB device copy measured
 # in the same runs), for the kernel as it was profiled; the summaries and
 # commands are in profiles/.  Keyed by (dtype, layout, kernel option, lattice).
-PROFILED_TRAFFIC_BYTES = {}
+PROFILED_TRAFFIC_BYTES = {
+    # k_step_tiled2<float, 8, true>, profiles/step_tiled2_512cubed.md
+    ("f32", 20, "auto", 512): 12.34e9,
+}
 
 
 def profiled_traffic(dt, layout, kernel, n):

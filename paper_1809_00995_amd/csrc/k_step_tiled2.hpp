@@ -20,6 +20,12 @@
 // momenta Pi, E of S_n are read by neighbouring blocks (their R1 ring) while
 // this block writes S_{n+2}: that is why every field has two copies.
 //
+// Per plane there are two barriers, both ordering LDS only: the global reads
+// of the next plane are issued one iteration ahead and stay in flight across
+// them.  Each site publishes its three forward plaquette sines in LDS (step
+// one's while staging, step two's after its S_{n+1} update), and the four it
+// needs from x-x and x-y are read there instead of recomputed.
+//
 // Both steps use leapfrog_site and plaq_sin, so S_{n+2} is bitwise what two
 // single-step tiled passes give.  When the second step of the pair is not
 // active (the realization reaches n_end after one step), the kernel writes

@@ -217,3 +217,29 @@ def test_two_step_batched_ensemble(prec):
                 assert a.step == b.step and a.n_wind_dir == b.n_wind_dir
                 if a.step >= 0:
                     assert a.energy == pytest.approx(b.energy, rel=1e-12)
+
+
+@pytest.mark.parametrize("layout", [L15, L20])
+def test_degenerate_calls(layout):
+    """Zero steps change nothing and measure nothing; a cadence longer than the call
+    measures only the states it meets (here the first); a frozen realization (n_end
+    reached) stays bitwise unchanged under further steps; ah_measure on a fresh
+    context sees the initial state."""
+    _print_case(test="degenerate", layout=layout)
+    p = AH.Params(64, 8, 6, precision=AH.AH_FP32, tau_ref=2.0, era_p=1.0, s=1.0, seed=81,
+                  layout=layout, n_end=5)
+    with AH.Context([p], [AH.alloc_planes(p)]) as c:
+        (m0,) = c.measure()
+        f0 = c.fields().clone()
+        assert c.step(0) == [] and c.current_step() == 0
+        assert c.step(0, measure_every=3) == []
+        assert torch.equal(c.fields(), f0)
+        obs = c.step(3, measure_every=100)
+        assert [o[0].step for o in obs] == [0]
+        assert obs[0][0].n_wind == m0.n_wind and obs[0][0].energy == pytest.approx(m0.energy, rel=1e-12)
+        c.step(10)
+        assert c.current_step() == 5
+        f5 = c.fields().clone()
+        obs = c.step(4, measure_every=1)
+        assert all(o[0].step == -1 for o in obs)   # frozen: slots left unmeasured
+        assert torch.equal(c.fields(), f5)
