@@ -162,10 +162,10 @@ def run_ensemble(AH, torch, batched, graph_steps, tune, layout=20):
     return total / sec, sec, tuning
 
 
-def cpu_baseline():
-    """The FP64 oracle (test infrastructure) on a bounded sample: 256^3, 24 steps."""
+def oracle_rate(n, k):
+    """Site-updates/s of the FP64 oracle (test infrastructure) over k steps of an n^3
+    matter-era lattice, and the seconds it took."""
     import oracle as O
-    n, k = 256, 24
     p = O.Params(n, n, n, tau0=1.0, tau_ref=n * 0.5 / 2, era_p=2.0, s=0.0, seed=2024)
     st = O.init_random_phase(p)
     st = O.step(p, 10, st)                     # warm the pages
@@ -173,9 +173,41 @@ def cpu_baseline():
     for i in range(k):
         st = O.step(p, 11 + i, st)
     dt = time.perf_counter() - t
-    return {"value": n ** 3 * k / dt, "unit": "site-updates/s", "cores": O.threads(),
-            "kind": "oracle",
-            "sample": f"FP64 CPU oracle, {n}^3 matter era s=0, {k} steps ({dt:.1f} s)"}
+    return n ** 3 * k / dt, dt
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline():
+    """The FP64 oracle on a bounded sample on this host: 256^3 x 24 steps on all the
+    threads OpenMP gives it, and 128^3 x 6 steps on one thread (a child process with
+    OMP_NUM_THREADS=1, which touches no GPU)."""
+    import subprocess
+    import oracle as O
+    n, k = 256, 24
+    rate, dt = oracle_rate(n, k)
+    out = {"value": rate, "unit": "site-updates/s", "cores": O.threads(), "kind": "oracle",
+           "sample": f"FP64 CPU oracle, {n}^3 matter era s=0, {k} steps ({dt:.1f} s)",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; r, dt = bench.oracle_rate(128, 6); "
+            "print(json.dumps([r, dt]))" % ROOT)
+    try:
+        res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                             timeout=120, env={**os.environ, "OMP_NUM_THREADS": "1"})
+        r1, dt1 = json.loads(res.stdout.strip().splitlines()[-1])
+        out["single_thread"] = {"value": r1, "sample": f"128^3, 6 steps ({dt1:.1f} s)"}
+    except (subprocess.SubprocessError, ValueError, IndexError) as e:
+        out["single_thread"] = {"value": None, "error": str(e)[:200]}
+    return out
 
 
 def main():

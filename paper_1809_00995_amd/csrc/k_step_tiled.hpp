@@ -83,9 +83,15 @@ __device__ __forceinline__ T plaq_omc(T aic, T ais, T bjc, T bjs, T cic, T cis, 
     return (T)0.5 * fma(a, a, b * b);
 }
 
-// wrap count of a link: [u]_pi = u - 2 pi m (Eq. (11)), computed in FP64
+// wrap count of a link: [u]_pi = u - 2 pi m (Eq. (11)), computed in FP64.
+// The quotient by 2 pi is taken as a product with its reciprocal (one FP64
+// multiply instead of a ~10-instruction correctly rounded division); the
+// two differ only when (u + pi) / 2 pi lies within an ulp of an integer,
+// i.e. u within ~1e-15 of an odd multiple of pi, where the phase
+// difference of the link is ambiguous anyway.
 __device__ __forceinline__ int wrap_count(double u) {
-    return (int)floor((u + kPi) / kTwoPi);
+    constexpr double kInvTwoPi = 0.15915494309189533576888376337251436;
+    return (int)floor((u + kPi) * kInvTwoPi);
 }
 
 template <typename T> struct SiteV {
@@ -631,6 +637,10 @@ inline int launch_step_tiled(bool fp64, int mode, const RealDesc *desc, const Co
                              int nx, int ny, int nz, int tile_y, int chunk_z, Slot *slot,
                              int8_t *wind, hipStream_t stream) {
     int ty = tile_y, cz = chunk_z;
+    // the measuring modes hold ~240 VGPRs (two waves per SIMD): 4-row tiles
+    // (two blocks per CU) are their default
+    if (ty <= 0 && mode != MODE_STEP)
+        ty = 4;
     tiled_defaults(fp64, nx, ny, nz, ty, cz);
     if (nx % 64 != 0 || !tiled_ty_valid(fp64, ty) || cz < 1)
         return (int)hipErrorInvalidValue;
