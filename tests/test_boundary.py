@@ -98,3 +98,13 @@ def test_bad_extents_alignment_and_null():
     assert lib.ah_step(None, 1, 0, None, 0, None) == B.AH_E_INVALID
     assert lib.ah_free(None) == B.AH_OK
     assert lib.ah_error_string(B.AH_E_NONFINITE) == b"non-finite field values"
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; --gpus N > 1 exits with a message before touching a GPU."""
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 2
+    assert "one GPU" in res.stderr and res.stdout == ""
