@@ -1,0 +1,119 @@
+"""The device sin/cos of the link phasors (ah_device.hpp), checked on the CPU.
+
+The constants are read from the header and the scheme (reduction by multiples
+of pi in two fused multiply-adds, odd and even minimax polynomials, sign flip
+for odd multiples) is replayed with every operation rounded to the working
+precision: float32 through numpy with fused multiply-adds taken exactly in
+float64 and rounded once; float64 through mpmath at 60 digits, rounded once per
+operation.  A mistyped coefficient or a wrong sign shows up as an error far
+above the bounds stated in the header.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                   "paper_1809_00995_amd", "csrc", "ah_device.hpp")
+NUM = re.compile(r"[-+]?\d+\.\d*(?:e[-+]?\d+)?f?")
+
+
+def _constants(sig):
+    src = open(HDR).read()
+    start = src.index(f"void sincos_t({sig} x")
+    body = src[src.index("{", start):src.index("\n}\n", start)]
+    vals = [float(v.rstrip("f")) for v in NUM.findall(body)]
+    # 1/pi, pi high, pi low, P (highest power first), Q (highest first), 1.0
+    return vals
+
+
+def _split(vals, n_p):
+    inv_pi, hi, lo = vals[:3]
+    p = vals[3:3 + n_p]
+    q = vals[3 + n_p:-1]
+    assert vals[-1] == 1.0
+    return inv_pi, hi, lo, p, q
+
+
+def _sincos_f32(x, consts):
+    inv_pi, hi, lo, p, q = consts
+    f32 = np.float32
+
+    def fma(a, b, c):
+        return (np.asarray(a, np.float64) * np.asarray(b, np.float64)
+                + np.asarray(c, np.float64)).astype(f32)
+
+    x = x.astype(f32)
+    k = np.rint((x * f32(inv_pi)).astype(f32))
+    r = fma(-k, f32(hi), x)
+    r = fma(-k, f32(lo), r)
+    u = (r * r).astype(f32)
+    ps = fma(u, f32(p[0]), f32(p[1]))
+    for c in p[2:]:
+        ps = fma(u, ps, f32(c))
+    s = fma((r * u).astype(f32), ps, r)
+    qs = fma(u, f32(q[0]), f32(q[1]))
+    for c in q[2:]:
+        qs = fma(u, qs, f32(c))
+    co = fma(u, qs, f32(1.0))
+    odd = (k.astype(np.int64) & 1) == 1
+    return np.where(odd, -s, s), np.where(odd, -co, co)
+
+
+def test_float_sincos_within_stated_error():
+    vals = _constants("float")
+    assert len(vals) == 3 + 4 + 5 + 1
+    consts = _split(vals, 4)
+    rng = np.random.default_rng(5)
+    for lim in (2.0, 40.0, 1e5):
+        x = rng.uniform(-lim, lim, 400_000).astype(np.float32)
+        s, c = _sincos_f32(x, consts)
+        xd = x.astype(np.float64)
+        assert np.abs(s - np.sin(xd)).max() < 1.5e-7, lim
+        assert np.abs(c - np.cos(xd)).max() < 1.5e-7, lim
+    # exact special cases and symmetry
+    z = np.array([0.0, -0.0], np.float32)
+    s, c = _sincos_f32(z, consts)
+    assert np.all(s == 0) and np.all(c == 1)
+    x = rng.uniform(-30, 30, 10_000).astype(np.float32)
+    s1, c1 = _sincos_f32(x, consts)
+    s2, c2 = _sincos_f32(-x, consts)
+    assert np.array_equal(s1, -s2) and np.array_equal(c1, c2)
+
+
+def test_double_sincos_within_stated_error():
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 60
+    vals = _constants("double")
+    assert len(vals) == 3 + 8 + 8 + 1
+    inv_pi, hi, lo, p, q = _split(vals, 8)
+    M = mp.mpf
+
+    def rnd(v):
+        return float(v)   # nearest double
+
+    def fma(a, b, c):
+        return rnd(M(a) * M(b) + M(c))
+
+    rng = np.random.default_rng(6)
+    worst = 0.0
+    for x in np.concatenate([rng.uniform(-2, 2, 600), rng.uniform(-300, 300, 600)]):
+        x = float(x)
+        k = float(np.rint(rnd(M(x) * M(inv_pi))))
+        r = fma(-k, hi, x)
+        r = fma(-k, lo, r)
+        u = rnd(M(r) * M(r))
+        ps = fma(u, p[0], p[1])
+        for cf in p[2:]:
+            ps = fma(u, ps, cf)
+        s = fma(rnd(M(r) * M(u)), ps, r)
+        qs = fma(u, q[0], q[1])
+        for cf in q[2:]:
+            qs = fma(u, qs, cf)
+        co = fma(u, qs, 1.0)
+        if int(k) & 1:
+            s, co = -s, -co
+        worst = max(worst, abs(M(s) - mp.sin(M(x))), abs(M(co) - mp.cos(M(x))))
+    # a few units of 2^-53 on results of magnitude up to 1
+    assert worst < 4 * 2.0 ** -53, float(worst)
