@@ -110,6 +110,8 @@ def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15):
 # in the same runs), for the kernel as it was profiled; the summaries and
 # commands are in profiles/.  Keyed by (dtype, layout, kernel option, lattice).
 PROFILED_TRAFFIC_BYTES = {
+    # k_step_tiled2<float, 9, true>, profiles/step_tiled2_512cubed.md
+    ("f32", 20, "auto", 512): 12.46e9,
 }
 
 

@@ -340,9 +340,14 @@ int build_items2(ah_ctx *c) {
         return AH_OK;
     const bool fp64 = c->prec == AH_FP64;
     int ty = c->tile_y2;
-    {
-        int z = 0;
-        tiled2_defaults(fp64, 64, 64, 64, ty, z);
+    if (ty <= 0) {
+        std::vector<int> nys(c->nreal);
+        std::vector<long> ws(c->nreal);
+        for (int r = 0; r < c->nreal; ++r) {
+            nys[r] = c->p[r].ny;
+            ws[r] = (long)c->p[r].nx * c->p[r].nz;
+        }
+        ty = tiled2_default_ty(fp64, nys.data(), ws.data(), c->nreal);
     }
     std::vector<int> order(c->nreal);
     for (int r = 0; r < c->nreal; ++r)
@@ -854,7 +859,7 @@ int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
     const bool two = use_tiled2(c);
     const int ty_cap = c->batched ? tiled_ty_max(fp64, MODE_STEP_MEASURE) : tiled_ty_max(fp64, MODE_STEP);
     std::vector<int> tys;
-    for (int t : { 4, 8, 16 })
+    for (int t : { 4, 5, 8, 9, 16 })
         if (two ? tiled2_ty_valid(fp64, t) : (tiled_ty_valid(fp64, t) && t <= ty_cap))
             tys.push_back(t);
 

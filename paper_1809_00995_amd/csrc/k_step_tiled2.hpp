@@ -516,15 +516,33 @@ k_step_batch2(const RealDesc *descs, const Coef *coefs, const BatchItem *items, 
     }
 }
 
-// Tile heights of the two-step kernel (LDS: FP32 94 KB at TY = 8, FP64
-// 120 KB at TY = 4; a workgroup may hold up to 160 KB on gfx950).
+// Tile heights of the two-step kernel.  LDS per block: FP32 112 KB at TY = 8,
+// 122 KB at TY = 9; FP64 143 KB at TY = 4, 163 KB at TY = 5 (a workgroup may
+// hold up to 160 KiB on gfx950).  TY = 9 (FP32) and TY = 5 (FP64) give 12 and
+// 8 wavefronts, an equal number on each of a CU's four SIMDs.
 inline bool tiled2_ty_valid(bool fp64, int ty) {
-    return ty == 4 || (!fp64 && ty == 8);
+    return fp64 ? (ty == 4 || ty == 5) : (ty == 4 || ty == 8 || ty == 9);
+}
+
+// Default tile height for lattices with the given y extents (weights: sites
+// per unit of y): the balanced height (9 FP32, 5 FP64) unless its ragged last
+// rows of tiles idle more than 2 % of the sites beyond the smaller height's.
+inline int tiled2_default_ty(bool fp64, const int *ny, const long *weight, int n) {
+    const int big = fp64 ? 5 : 9, small = big - 1;
+    double pad_big = 0, pad_small = 0, total = 0;
+    for (int i = 0; i < n; ++i) {
+        pad_big += (double)weight[i] * ((ny[i] + big - 1) / big * big - ny[i]);
+        pad_small += (double)weight[i] * ((ny[i] + small - 1) / small * small - ny[i]);
+        total += (double)weight[i] * ny[i];
+    }
+    return pad_big <= pad_small + 0.02 * total ? big : small;
 }
 
 inline void tiled2_defaults(bool fp64, int nx, int ny, int nz, int &ty, int &cz) {
-    if (ty <= 0)
-        ty = fp64 ? 4 : 8;
+    if (ty <= 0) {
+        const long w = (long)nx * nz;
+        ty = tiled2_default_ty(fp64, &ny, &w, 1);
+    }
     if (cz <= 0) {
         // long chunks amortise the two extra planes of step one; aim at ~2048 blocks
         const long tiles_xy = (long)(nx / 64) * ((ny + ty - 1) / ty);
@@ -565,10 +583,14 @@ inline int launch_step_tiled2(bool fp64, const RealDesc *desc, const Coef *coef,
     if (nx % 64 != 0 || !tiled2_ty_valid(fp64, ty) || cz < 1)
         return (int)hipErrorInvalidValue;
     hipError_t e;
-    if (fp64)
+    if (fp64 && ty == 5)
+        e = launch_tiled2_ty<double, 5>(desc, coef, r, nreal, nx, ny, nz, cz, stream);
+    else if (fp64)
         e = launch_tiled2_ty<double, 4>(desc, coef, r, nreal, nx, ny, nz, cz, stream);
     else if (ty == 4)
         e = launch_tiled2_ty<float, 4>(desc, coef, r, nreal, nx, ny, nz, cz, stream);
+    else if (ty == 9)
+        e = launch_tiled2_ty<float, 9>(desc, coef, r, nreal, nx, ny, nz, cz, stream);
     else
         e = launch_tiled2_ty<float, 8>(desc, coef, r, nreal, nx, ny, nz, cz, stream);
     return (int)e;
@@ -613,10 +635,14 @@ inline int batch2_dispatch(bool fp64, int ty, bool off32, const RealDesc *desc, 
     (off32 ? batch2_ty<T, TY_, true>(desc, coef, items, n_items, nreal, grid, stream, grid_out)    \
            : batch2_ty<T, TY_, false>(desc, coef, items, n_items, nreal, grid, stream, grid_out))
     hipError_t e;
-    if (fp64)
+    if (fp64 && ty == 5)
+        e = AH_B2(double, 5);
+    else if (fp64)
         e = AH_B2(double, 4);
     else if (ty == 4)
         e = AH_B2(float, 4);
+    else if (ty == 9)
+        e = AH_B2(float, 9);
     else
         e = AH_B2(float, 8);
 #undef AH_B2

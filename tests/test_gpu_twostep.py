@@ -62,7 +62,7 @@ def test_two_step_bitwise_equals_single_steps(prec, shape):
     two-step kernel equal single-step tiled runs in the 15-plane layout bit for
     bit, for every tile height and a few z-chunks (one plane, ragged, whole)."""
     st = I.random_state(shape, seed=808)
-    tys = [4] if prec == AH.AH_FP64 else [4, 8]
+    tys = [4, 5] if prec == AH.AH_FP64 else [4, 8, 9]
     ref_p = _params(shape, prec, L15)
     with _ctx(ref_p, upload(ref_p, st), AH.AH_KERNEL_TILED) as c:
         refs = []
