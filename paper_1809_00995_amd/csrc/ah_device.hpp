@@ -103,7 +103,7 @@ __host__ __device__ __forceinline__ int plane_count(int layout) {
 // k = rint(x / pi), r = x - k pi from pi split in a high and a low part (one
 // fused multiply-add each, so |r| <= pi/2 to within half an ulp of r); then
 //   sin r = r + r^3 P(r^2),   cos r = 1 + r^2 Q(r^2),
-// with P and Q the minimax polynomials printed by fit_sincos.py (Remez
+// with P and Q the minimax polynomials printed by fit_polys.py (Remez
 // exchange on 0 <= r <= pi/2: relative error of sin r, absolute error of
 // cos r), and both signs flip for odd k.  Float: about 20 vector instructions,
 // absolute error below 1.5e-7 (about 2 ulp of results near 1) for |x| < 1e5;
@@ -152,6 +152,31 @@ __device__ __forceinline__ void sincos_t(double x, double *s, double *c) {
     const unsigned long long sign = (unsigned long long)(long long)k << 63;
     *s = __longlong_as_double((long long)((unsigned long long)__double_as_longlong(sr) ^ sign));
     *c = __longlong_as_double((long long)((unsigned long long)__double_as_longlong(cr) ^ sign));
+}
+
+// FP32 phase arg(x + iy) in [-pi, pi], the quadrant and signs taken as atan2
+// takes them (signed zeros included): a = min(|x|,|y|) / max(|x|,|y|) from a
+// hardware reciprocal, atan a = a + a^3 T(a^2) with the minimax T printed by
+// fit_polys.py, then pi/2 - . for |y| > |x|, pi - . for negative x, and the
+// sign of y.  Absolute error below 5e-7 (4.3e-7 measured over all octants and
+// 40 decades of magnitude).  Returns NaN when max(|x|,|y|) is below 1e-30 or
+// not finite, so that callers take the FP64 phase instead.
+__device__ __forceinline__ float phase_f32(float y, float x) {
+    const float ax = __builtin_fabsf(x), ay = __builtin_fabsf(y);
+    const float mx = __builtin_fmaxf(ax, ay), mn = __builtin_fminf(ax, ay);
+    const float a = mn * __builtin_amdgcn_rcpf(mx);
+    const float u = a * a;
+    float t = __builtin_fmaf(u, -4.822534e-03f, 2.4734063e-02f);
+    t = __builtin_fmaf(u, t, -6.0203128e-02f);
+    t = __builtin_fmaf(u, t, 9.968473e-02f);
+    t = __builtin_fmaf(u, t, -1.4041328e-01f);
+    t = __builtin_fmaf(u, t, 1.9974214e-01f);
+    t = __builtin_fmaf(u, t, -3.3332393e-01f);
+    float r = __builtin_fmaf(a * u, t, a);
+    r = ay > ax ? 1.5707964e+00f - r : r;
+    r = __builtin_signbit(x) ? 3.1415927e+00f - r : r;
+    r = __builtin_copysignf(r, y);
+    return (mx >= 1e-30f && mx <= 3.0e38f) ? r : __builtin_nanf("");
 }
 
 template <typename T> __device__ __forceinline__ T sin_t(T x) {

@@ -1,13 +1,19 @@
-"""Generator of the polynomial coefficients of the device sincos (ah_device.hpp).
+"""Generator of the polynomial coefficients of the device sin/cos and arctangent
+(ah_device.hpp).
 
-The device reduces x by multiples of pi, x = k*pi + r with |r| <= pi/2, and
-evaluates
+sincos: the device reduces x by multiples of pi, x = k*pi + r with |r| <= pi/2,
+and evaluates
     sin r = r + r^3 * P(r^2),    cos r = 1 + r^2 * Q(r^2),
 flipping both signs for odd k.  P is the minimax fit (relative error of sin r)
-and Q the minimax fit (absolute error of cos r) on 0 <= r <= pi/2, found here by
-the Remez exchange algorithm on a dense grid in 50-digit arithmetic (mpmath),
-then rounded to the working precision.  Run with no arguments to print both
-sets; the header holds the printed values.
+and Q the minimax fit (absolute error of cos r) on 0 <= r <= pi/2.
+
+arctangent (FP32 phase of the winding filter): atan a = a + a^3 * T(a^2) on
+0 <= a <= 1 (the ratio of the smaller to the larger of |x|, |y|), minimax in
+relative error.
+
+All fits use the Remez exchange algorithm on a dense grid in 50-digit
+arithmetic (mpmath), then round to the working precision.  Run with no
+arguments to print every set; the header holds the printed values.
 """
 import mpmath as mp
 import numpy as np
@@ -16,10 +22,9 @@ mp.mp.dps = 50
 HALF_PI = mp.pi / 2
 
 
-def remez(n, target, weight, grid_pts=4000, iters=40):
-    """Minimax polynomial sum_j c_j u^j (n terms) of target(u) on (0, (pi/2)^2]
-    for the weighted error weight(u) * (p(u) - target(u))."""
-    U = HALF_PI ** 2
+def remez(n, target, weight, grid_pts=4000, iters=40, U=HALF_PI ** 2):
+    """Minimax polynomial sum_j c_j u^j (n terms) of target(u) on (0, U] for the
+    weighted error weight(u) * (p(u) - target(u))."""
     grid = [U * (1 - mp.cos(mp.pi * (i + 0.5) / grid_pts)) / 2 for i in range(grid_pts)]
     grid[-1] = U
     tv = [target(u) for u in grid]
@@ -73,6 +78,15 @@ def cos_tail(u):
     return (mp.cos(mp.sqrt(u)) - 1) / u if u > 0 else mp.mpf(-1) / 2
 
 
+def atan_tail(u):
+    a = mp.sqrt(u)
+    return (mp.atan(a) - a) / (a * u) if u > 0 else mp.mpf(-1) / 3
+
+
+def fit_atan(n):
+    return remez(n, atan_tail, lambda u: u * mp.sqrt(u) / mp.atan(mp.sqrt(u)), U=mp.mpf(1))
+
+
 def fit(n_sin, n_cos):
     ps, es = remez(n_sin, sin_tail, lambda u: u * mp.sqrt(u) / mp.sin(mp.sqrt(u)))
     pc, ec = remez(n_cos, cos_tail, lambda u: u)
@@ -96,6 +110,12 @@ def main():
         lo = mp.pi - mp.mpf(float(hi))
         print("1/pi, pi high, pi low:", rounded(1 / mp.pi, name), rounded(mp.mpf(float(hi)), name),
               rounded(lo, name))
+
+
+    pa, ea = fit_atan(7)
+    print(f"// float arctangent: rel. error {mp.nstr(ea, 3)}")
+    print("T (a^0 first):", ", ".join(rounded(v, "float") for v in pa))
+    print("pi/2, pi:", rounded(HALF_PI, "float"), rounded(mp.pi, "float"))
 
 
 if __name__ == "__main__":

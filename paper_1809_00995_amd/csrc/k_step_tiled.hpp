@@ -89,14 +89,33 @@ __device__ __forceinline__ T plaq_omc(T aic, T ais, T bjc, T bjs, T cic, T cis, 
 // two differ only when (u + pi) / 2 pi lies within an ulp of an integer,
 // i.e. u within ~1e-15 of an odd multiple of pi, where the phase
 // difference of the link is ambiguous anyway.
+constexpr double kInvTwoPi = 0.15915494309189533576888376337251436;
+
 __device__ __forceinline__ int wrap_count(double u) {
-    constexpr double kInvTwoPi = 0.15915494309189533576888376337251436;
     return (int)floor((u + kPi) * kInvTwoPi);
+}
+
+// The measuring kernels decide wrap counts on FP32 phases (phase_f32, error
+// below 5e-7) and fall back to FP64 phases (atan2) for every link of a site
+// when any of its quotients (u + pi) / 2 pi lies within kWrapMargin of an
+// integer: the two sets of phases move a quotient by at most ~1.6e-7, so
+// outside the margin both give the same integer, and the counts equal those
+// of FP64 phases everywhere.
+constexpr double kWrapMargin = 4e-6;
+
+// m = wrap_count(u) from FP32 phases; false when the FP64 phases must decide
+// (u within the margin of a boundary, or not a number).
+__device__ __forceinline__ bool wrap_count_sure(double u, int &m) {
+    const double w = (u + kPi) * kInvTwoPi;
+    const double f = floor(w);
+    m = (int)f;
+    const double fr = w - f;
+    return fr > kWrapMargin && fr < 1.0 - kWrapMargin;
 }
 
 template <typename T> struct SiteV {
     T pr, pm, ax, ay, az, uxc, uxs, uyc, uys, uzc, uzs;
-    double th;
+    float th;   // FP32 phase (measuring kernels)
 };
 
 // Everything the update of one site x reads (Eqs. (4)-(7)), gathered by the
@@ -204,27 +223,35 @@ __device__ __forceinline__ void meas_init(MeasAcc &m, const RealDesc &d, const C
 
 // What the measurement of site x reads: its fields and phasors, phi at
 // x+x, x+y, x+z, the phasors of the other links of its three forward
-// plaquettes, and arg(phi) (FP64) and the raw link angles at the corners of
-// those plaquettes.
+// plaquettes, and the FP32 phases of phi and the raw link angles at the
+// corners of those plaquettes.
 template <typename T> struct MeasSite {
     T pr, pm, pr0, pi0, ax, ay, az, ex0, ey0, ez0;
     T uxc, uxs, uyc, uys, uzc, uzs;
     T pr_xp, pi_xp, pr_yp, pi_yp, pr_zp, pi_zp;
     T uyc_xp, uys_xp, uzc_xp, uzs_xp, uxc_yp, uxs_yp, uzc_yp, uzs_yp, uxc_zp, uxs_zp, uyc_zp, uys_zp;
-    double th, th_xp, th_yp, th_xpyp, th_zp, th_xpzp, th_ypzp;
+    float th, th_xp, th_yp, th_xpyp, th_zp, th_xpzp, th_ypzp;
     double ay_xp, az_xp, ax_yp, az_yp, ax_zp, ay_zp;
+};
+
+// phi at the corners x+x+y, x+x+z, x+y+z of the forward plaquettes (read
+// only when the winding falls back to FP64 phases).
+template <typename T> struct Corners {
+    T pr_xpyp, pi_xpyp, pr_xpzp, pi_xpzp, pr_ypzp, pi_ypzp;
 };
 
 // Add site x of S_n to the accumulators: the densities of Eqs. (9)-(10), the
 // pressure of Eq. (12), and the windings of its xy, yz, zx plaquettes
 // (Eq. (11)) from the wrap counts of their links; w3 receives the windings.
-template <typename T>
-__device__ __forceinline__ void measure_site(MeasAcc &m, const MeasSite<T> &v, int (&w3)[3]) {
-    const bool finite = isfinite((double)v.pr) && isfinite((double)v.pm) &&
-                        isfinite((double)v.pr0) && isfinite((double)v.pi0) &&
-                        isfinite((double)v.ax) && isfinite((double)v.ay) &&
-                        isfinite((double)v.az) && isfinite((double)v.ex0) &&
-                        isfinite((double)v.ey0) && isfinite((double)v.ez0);
+// corners() returns the Corners of the site.
+template <typename T, typename CornersFn>
+__device__ __forceinline__ void measure_site(MeasAcc &m, const MeasSite<T> &v, int (&w3)[3],
+                                             CornersFn corners) {
+    const bool finite = __builtin_isfinite(v.pr) && __builtin_isfinite(v.pm) &&
+                        __builtin_isfinite(v.pr0) && __builtin_isfinite(v.pi0) &&
+                        __builtin_isfinite(v.ax) && __builtin_isfinite(v.ay) &&
+                        __builtin_isfinite(v.az) && __builtin_isfinite(v.ex0) &&
+                        __builtin_isfinite(v.ey0) && __builtin_isfinite(v.ez0);
     w3[0] = w3[1] = w3[2] = 0;
     if (!finite) {
         m.c[C_NONFIN] += 1;
@@ -250,7 +277,10 @@ __device__ __forceinline__ void measure_site(MeasAcc &m, const MeasSite<T> &v, i
     const double V = 0.25 * vv * vv;
     const double lag = ma2 * K - ma2 * Gr + mg * (EE - BB) - mh * V;
     const double rho = ma2 * K + ma2 * Gr + mg * (EE + BB) + mh * V;
-    const double pres = ma2 * K - ma2 * Gr / 3.0 + mg * (EE + BB) / 3.0 - mh * V;
+    // the thirds as products with 1/3 (two FP64 divisions per site saved; the
+    // results differ from the quotients by at most an ulp of each term)
+    constexpr double kThird = 1.0 / 3.0;
+    const double pres = ma2 * K - (ma2 * Gr) * kThird + (mg * (EE + BB)) * kThird - mh * V;
     m.s[A_KIN] += ma2 * K;
     m.s[A_GRAD] += ma2 * Gr;
     m.s[A_ELEC] += mg * EE;
@@ -267,17 +297,39 @@ __device__ __forceinline__ void measure_site(MeasAcc &m, const MeasSite<T> &v, i
     m.s[A_PRES_L] += pres * lag;
     m.s[A_RHO_L] += rho * lag;
 
-    // winding (Eq. (11)) from link wrap counts
+    // winding (Eq. (11)) from link wrap counts: FP32 phases, FP64 near a boundary
     const double ax = v.ax, ay = v.ay, az = v.az;
-    const int mx = wrap_count(v.th_xp - v.th + ax);
-    const int my = wrap_count(v.th_yp - v.th + ay);
-    const int mz = wrap_count(v.th_zp - v.th + az);
-    const int my_xp = wrap_count(v.th_xpyp - v.th_xp + v.ay_xp);
-    const int mx_yp = wrap_count(v.th_xpyp - v.th_yp + v.ax_yp);
-    const int mz_yp = wrap_count(v.th_ypzp - v.th_yp + v.az_yp);
-    const int my_zp = wrap_count(v.th_ypzp - v.th_zp + v.ay_zp);
-    const int mx_zp = wrap_count(v.th_xpzp - v.th_zp + v.ax_zp);
-    const int mz_xp = wrap_count(v.th_xpzp - v.th_xp + v.az_xp);
+    const double t = v.th, t_xp = v.th_xp, t_yp = v.th_yp, t_zp = v.th_zp;
+    const double t_xpyp = v.th_xpyp, t_xpzp = v.th_xpzp, t_ypzp = v.th_ypzp;
+    int mx, my, mz, my_xp, mx_yp, mz_yp, my_zp, mx_zp, mz_xp;
+    bool sure = wrap_count_sure(t_xp - t + ax, mx);
+    sure &= wrap_count_sure(t_yp - t + ay, my);
+    sure &= wrap_count_sure(t_zp - t + az, mz);
+    sure &= wrap_count_sure(t_xpyp - t_xp + v.ay_xp, my_xp);
+    sure &= wrap_count_sure(t_xpyp - t_yp + v.ax_yp, mx_yp);
+    sure &= wrap_count_sure(t_ypzp - t_yp + v.az_yp, mz_yp);
+    sure &= wrap_count_sure(t_ypzp - t_zp + v.ay_zp, my_zp);
+    sure &= wrap_count_sure(t_xpzp - t_zp + v.ax_zp, mx_zp);
+    sure &= wrap_count_sure(t_xpzp - t_xp + v.az_xp, mz_xp);
+    if (!sure) {
+        const Corners<T> k = corners();
+        const double e = atan2((double)v.pm, (double)v.pr);
+        const double e_xp = atan2((double)v.pi_xp, (double)v.pr_xp);
+        const double e_yp = atan2((double)v.pi_yp, (double)v.pr_yp);
+        const double e_zp = atan2((double)v.pi_zp, (double)v.pr_zp);
+        const double e_xpyp = atan2((double)k.pi_xpyp, (double)k.pr_xpyp);
+        const double e_xpzp = atan2((double)k.pi_xpzp, (double)k.pr_xpzp);
+        const double e_ypzp = atan2((double)k.pi_ypzp, (double)k.pr_ypzp);
+        mx = wrap_count(e_xp - e + ax);
+        my = wrap_count(e_yp - e + ay);
+        mz = wrap_count(e_zp - e + az);
+        my_xp = wrap_count(e_xpyp - e_xp + v.ay_xp);
+        mx_yp = wrap_count(e_xpyp - e_yp + v.ax_yp);
+        mz_yp = wrap_count(e_ypzp - e_yp + v.az_yp);
+        my_zp = wrap_count(e_ypzp - e_zp + v.ay_zp);
+        mx_zp = wrap_count(e_xpzp - e_zp + v.ax_zp);
+        mz_xp = wrap_count(e_xpzp - e_xp + v.az_xp);
+    }
     w3[0] = -(mx + my_xp - mx_yp - my);
     w3[1] = -(my + mz_yp - my_zp - mz);
     w3[2] = -(mz + mx_zp - mz_xp - mx);
@@ -323,7 +375,7 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
     using G = TileGeom<TY>;
     constexpr int SM = MEAS ? G::S : 1;
     __shared__ T lds[2][Q_COUNT][G::S];
-    __shared__ double lth[2][SM];      // arg phi (measuring modes)
+    __shared__ float lth[2][SM];       // FP32 phase of phi (measuring modes)
     __shared__ T lar[2][3][SM];        // raw link angles (measuring modes)
 
     const int nx = d.nx, ny = d.ny, nz = d.nz;
@@ -372,7 +424,7 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
         sincos_t(v.ay, &v.uys, &v.uyc);
         sincos_t(v.az, &v.uzs, &v.uzc);
         if (MEAS)
-            v.th = atan2((double)v.pm, (double)v.pr);
+            v.th = phase_f32((float)v.pm, (float)v.pr);
     };
     auto put = [&](int bf, int k, const SiteV<T> &v) {
         lds[bf][Q_PR][k] = v.pr;
@@ -516,7 +568,16 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
             mv.ax_yp = lar[cb][0][q + G::W]; mv.az_yp = lar[cb][2][q + G::W];
             mv.ax_zp = nxt.ax; mv.ay_zp = nxt.ay;
             int w3[3];
-            measure_site(macc, mv, w3);
+            measure_site(macc, mv, w3, [&]() {
+                Corners<T> k;
+                k.pr_xpyp = L[Q_PR][q + 1 + G::W];
+                k.pi_xpyp = L[Q_PI][q + 1 + G::W];
+                k.pr_xpzp = Ln[Q_PR][q + 1];
+                k.pi_xpzp = Ln[Q_PI][q + 1];
+                k.pr_ypzp = Ln[Q_PR][q + G::W];
+                k.pi_ypzp = Ln[Q_PI][q + G::W];
+                return k;
+            });
             if (MODE == MODE_MEASURE && wind)
                 for (int k = 0; k < 3; ++k)
                     wind[(size_t)k * (size_t)d.N + s] = (int8_t)w3[k];

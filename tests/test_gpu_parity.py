@@ -159,6 +159,59 @@ def test_measure_and_wind_map_match_oracle(O, prec, kernel):
         assert g.energy == pytest.approx(o.energy, rel=rel)
 
 
+def _plant_near_boundaries(st, prec, seed, frac=0.4, spread=3e-5):
+    """Set the angle of a fraction of the links so that the winding argument
+    theta^{x+i} - theta^x + A_i of Eq. (11) lies within +-spread of an odd
+    multiple of pi (shifted by -2 pi, 0 or 2 pi), rounded to the storage
+    precision; returns the number of links within 2.6e-5 of a boundary."""
+    rng = np.random.default_rng(seed)
+    th = np.arctan2(st[1], st[0])
+    near = 0
+    for i, axis in enumerate((2, 1, 0)):
+        u0 = np.roll(th, -1, axis=axis) - th
+        pick = rng.random(th.shape) < frac
+        k = rng.integers(-1, 2, size=th.shape)
+        a = np.pi - u0 + rng.uniform(-spread, spread, size=th.shape) + 2 * np.pi * k
+        if prec == AH.AH_FP32:
+            a = a.astype(np.float32).astype(np.float64)
+        st[4 + i] = np.where(pick, a, st[4 + i])
+        r = np.mod(u0 + st[4 + i] + np.pi, 2 * np.pi)
+        near += int((np.minimum(r, 2 * np.pi - r) < 2.6e-5).sum())
+    return near
+
+
+@pytest.mark.parametrize("prec", [AH.AH_FP64, AH.AH_FP32])
+def test_winding_near_link_boundaries(O, prec):
+    """Links planted around the branch points of [.]_pi (Eq. (11)), within and
+    beyond the band where the measuring kernels decide wrap counts from FP64
+    instead of FP32 phases: winding map (read-only measurement, tiled and
+    plain kernels) and the counts of the fused step measurement equal the
+    oracle's at every plaquette whose links are not within 1e-9 of a tie."""
+    shape = (64, 10, 9)
+    _print_case(test="wind_near_boundaries", prec=prec)
+    p = AH.Params(*shape, precision=prec, tau0=3.0, tau_ref=4.0, era_p=2.0, s=0.0,
+                  init=AH.AH_INIT_NONE, step0=7)
+    st = I.random_state(shape, seed=515, amp_a=2.5)
+    if prec == AH.AH_FP32:
+        st = st.astype(np.float32).astype(np.float64)
+    near = _plant_near_boundaries(st, prec, seed=516)
+    assert near > 1000   # the FP64 fallback is exercised at many sites
+    o = O.measure(oracle_params(O, p), 7, st, wind_map=True)
+    allowed = plaquette_touches(ambiguous_links(st, tol=1e-9))
+    for kernel in (AH.AH_KERNEL_TILED, AH.AH_KERNEL_PLAIN):
+        with _ctx(p, upload(p, st), kernel) as c:
+            (g,), (w,) = c.measure(wind=True)
+            w = w.cpu().numpy().astype(np.int64)
+            (f,), = c.step(1, measure_every=1)
+        diff = w != o.wind
+        assert not (diff & ~allowed).any(), (kernel, int((diff & ~allowed).sum()))
+        if not allowed.any():
+            for obs in (g, f):
+                assert obs.step == 7
+                assert obs.n_wind_dir == o.n_wind_dir and obs.net_wind_dir == o.net_wind_dir
+                assert obs.n_pierced == o.n_pierced
+
+
 @pytest.mark.parametrize("prec", [AH.AH_FP64, AH.AH_FP32])
 def test_gauss_residual_matches_oracle(O, prec):
     shape = (64, 7, 6)
