@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -103,6 +104,76 @@ def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15):
     return {"rate": n ** 3 * steps / (ms * 1e-3), "ms_per_step": ms / steps,
             "rate_no_diag": n ** 3 * steps / (ms_nd * 1e-3), "kernel_ms": kt[len(kt) // 2],
             "kernel_ms_mean": sum(kt) / len(kt), "launches_timed": k, "per": per, "last": last}
+
+
+def run_slab(AH, torch, passes=30, nxy=1024, nz=128):
+    """One GPU's share of a z-decomposed 1024^3 lattice over 8 GPUs: an nxy x nxy x nz
+    FP32 slab with two halo planes a side (20-plane layout, two steps per pass).  The
+    halo of the current copy is refilled before every pass from the slab's own opposite
+    faces by device copies, standing in for the exchange with the z neighbours."""
+    H = 2
+    p = AH.Params(nxy, nxy, nz, precision=AH.AH_FP32, dx=0.5, dt=0.1, tau0=1.0,
+                  tau_ref=nxy * 0.25, era_p=2.0, s=0.0, init=AH.AH_INIT_VACUUM,
+                  layout=AH.AH_LAYOUT_20, z_halo=H)
+    planes = AH.alloc_planes(p)
+    ctx = AH.Context([p], [planes])
+    stream = torch.cuda.current_stream()
+
+    def refill():
+        c0 = ctx.current_planes(0)[0]         # the ten fields of a copy are contiguous
+        cur = planes[c0:c0 + 10]
+        cur[:, :H] = cur[:, nz:nz + H]
+        cur[:, H + nz:] = cur[:, H:2 * H]
+
+    # a non-trivial state: random phases on the slab
+    g = torch.Generator(device="cuda").manual_seed(7)
+    th = torch.rand((nz, nxy, nxy), generator=g, device="cuda") * (2 * math.pi) - math.pi
+    planes[0, H:H + nz] = torch.cos(th)
+    planes[1, H:H + nz] = torch.sin(th)
+    del th
+    refill()
+    for _ in range(3):
+        ctx.step(2)
+        refill()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(passes):
+        ctx.step(2)
+        refill()
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    kt, ct = [], []
+    for _ in range(10):
+        a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        a.record(stream)
+        ctx.step(2)
+        b.record(stream)
+        refill()
+        c.record(stream)
+        torch.cuda.synchronize()
+        kt.append(a.elapsed_time(b))
+        ct.append(b.elapsed_time(c))
+    ctx.close()
+    del planes
+    torch.cuda.empty_cache()
+    kt.sort()
+    ct.sort()
+    sites = nxy * nxy * nz
+    plane_bytes = nxy * nxy * 4
+    # per pass and face: phi, A on two planes, Pi, E on one (15 plane-values)
+    face_bytes = 15 * plane_bytes
+    return {"workload": f"{nxy}x{nxy}x{nz} FP32 z-slab (one GPU's share of a {nxy}^3 lattice "
+                        f"over {nxy // nz} GPUs), {H} halo planes a side refilled by device "
+                        "copies from its own faces before every two-step pass",
+            "value": sites * 2 * passes / (ms * 1e-3), "unit": "site-updates/s",
+            "ms_per_pass": ms / passes, "kernel_ms": kt[len(kt) // 2],
+            "halo_refill_ms": ct[len(ct) // 2],
+            "kernel_frac": BYTES_PER_SITE["f32"] * sites * 2 / (kt[len(kt) // 2] * 1e-3) / 1e9
+            / HBM_PEAK_GBS,
+            "exchange_bytes_per_face_per_pass": face_bytes,
+            "exchange_ms_at_153GBs_per_link": face_bytes / 153e9 * 1e3}
 
 
 # HBM bytes per launch of the dominant kernel from the profiler's byte counters
@@ -213,8 +284,9 @@ def cpu_baseline():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the multi-GPU "
-              "z-slab decomposition of the lattice is not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the exchange between "
+              "z-slabs on several GPUs is not built (its 'slab' form times one GPU's share)",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1809_00995_amd as AH
@@ -277,6 +349,10 @@ def main():
                               "kernel_ms": fp["kernel_ms"], "steps": kp}
         line["speedup_fp32_vs_plain_fp64"] = rate32 / fp["rate"]
         line["speedup_fp64_vs_plain_fp64"] = line["fp64"]["value"] / fp["rate"]
+        line["slab"] = run_slab(AH, torch)
+        print(f"# slab: {line['slab']['value']:.4g} site-updates/s, kernel "
+              f"{line['slab']['kernel_ms']:.3f} ms + halo refill "
+              f"{line['slab']['halo_refill_ms']:.3f} ms per pass", file=sys.stderr, flush=True)
     if not args.no_secondary and not args.no_ensemble:
         rb, sb, tuning = run_ensemble(AH, torch, True, 10, True)
         rs, ss, _ = run_ensemble(AH, torch, False, 0, False)

@@ -22,7 +22,8 @@
  *    unless it returns observations; ah_measure and ah_gauss_residual
  *    synchronise that stream before returning host values.
  *  - Field layout (struct ah_buffers): 15 planes of nx*ny*nz elements
- *    (float for AH_FP32, double for AH_FP64), contiguous, site index
+ *    (nx*ny*(nz + 2 z_halo) for a slab, see "Slabs" below; float for
+ *    AH_FP32, double for AH_FP64), contiguous, site index
  *    idx = x + nx*(y + ny*z), in the order
  *      0 phi_re  1 phi_im  2 Pi_re  3 Pi_im  4 A_x  5 A_y  6 A_z
  *      7 E_x     8 E_y     9 E_z   10 phi_re' 11 phi_im' 12 A_x' 13 A_y' 14 A_z'
@@ -101,7 +102,29 @@ typedef struct ah_params {
                              e.g. a core-growth period (s < 0) followed by the true
                              equations of motion (s_late = 1), Sec. 2 after Eq. (8);
                              tau_s <= 0: s throughout                                   */
+    int32_t z_halo;       /* 0: periodic in z.  1 or 2: the realization is a z-slab of
+                             a larger lattice (one GPU's share of a z-decomposed run):
+                             see "Slabs" below                                          */
+    int32_t reserved;     /* must be 0                                                  */
 } ah_params;
+
+/*
+ * Slabs (z_halo = H > 0).  Every field plane holds nz + 2H z-planes: planes
+ * [0, H) are the halo below the slab, [H, H + nz) the slab, [H + nz, nz + 2H)
+ * the halo above (site index x + nx*(y + ny*z) over the stored planes).  Only
+ * the slab's planes are advanced and measured (box volume nx*ny*nz dx^3); the
+ * halo planes are read, never written.  Before every ah_step and ah_measure
+ * call the caller fills all ten fields of the current copy
+ * (ah_current_planes) on every halo plane with the neighbouring slabs' planes
+ * of the same state: on several GPUs that is the exchange with the z
+ * neighbours; a slab closed on itself (halo below = its top planes, halo
+ * above = its bottom planes) is a periodic lattice.  ah_step then advances one
+ * pass per call: nsteps = 1, or nsteps = 2 when H = 2, the two-step kernel is
+ * in use and no measurement is due at the first step.  Requirements: the
+ * tiled kernels (nx % 64 == 0), unbatched launches without graphs,
+ * AH_INIT_NONE or AH_INIT_VACUUM; ah_gauss_residual and ah_autotune are not
+ * available (AH_E_INVALID / AH_E_STATE otherwise).
+ */
 
 /* Caller-owned device memory of one realization: 15 or 20 planes (per
  * layout), see above.  Alignment: 256 bytes. */
@@ -167,7 +190,8 @@ int ah_init(ah_ctx **ctx, int32_t n_real, const ah_params *p, const ah_buffers *
  * out_cap is the capacity of out in states per realization; the call fails
  * with AH_E_INVALID, before any work, if it is too small.  With out == NULL
  * (and measure_every = 0) the call only enqueues work and returns at once.
- * Returns AH_E_NONFINITE if a measurement saw non-finite values.
+ * Returns AH_E_NONFINITE if a measurement saw non-finite values.  A context
+ * holding slabs (z_halo > 0) advances one pass per call, see "Slabs".
  */
 int ah_step(ah_ctx *ctx, int64_t nsteps, int32_t measure_every, ah_obs *out,
             int64_t out_cap, int64_t *n_out);

@@ -44,7 +44,8 @@ class _Params(C.Structure):
                 ("lambda0", C.c_double), ("e0", C.c_double), ("sigma", C.c_double),
                 ("seed", C.c_uint64), ("init", C.c_int32), ("layout", C.c_int32),
                 ("step0", C.c_int64), ("n_end", C.c_int64),
-                ("s_late", C.c_double), ("tau_s", C.c_double)]
+                ("s_late", C.c_double), ("tau_s", C.c_double),
+                ("z_halo", C.c_int32), ("reserved", C.c_int32)]
 
 
 class _Buffers(C.Structure):
@@ -121,12 +122,13 @@ class Params:
     s_late: float = 1.0
     tau_s: float = 0.0
     layout: int = AH_LAYOUT_15
+    z_halo: int = 0
 
     def _c(self) -> _Params:
         return _Params(self.nx, self.ny, self.nz, self.precision, self.dx, self.dt, self.tau0,
                        self.tau_ref, self.era_p, self.s, self.lambda0, self.e0, self.sigma,
                        self.seed & 0xFFFFFFFFFFFFFFFF, self.init, self.layout, self.step0,
-                       self.n_end, self.s_late, self.tau_s)
+                       self.n_end, self.s_late, self.tau_s, self.z_halo, 0)
 
     @property
     def planes(self) -> int:
@@ -137,8 +139,14 @@ class Params:
         return torch.float64 if self.precision == AH_FP64 else torch.float32
 
     @property
+    def nz_stored(self) -> int:
+        """z-planes held per field plane: nz, plus the halo planes of a slab."""
+        return self.nz + 2 * self.z_halo
+
+    @property
     def sites(self) -> int:
-        return self.nx * self.ny * self.nz
+        """Stored sites per field plane."""
+        return self.nx * self.ny * self.nz_stored
 
 
 @dataclass
@@ -180,8 +188,8 @@ class Obs:
 
 def alloc_planes(p: Params, device="cuda") -> torch.Tensor:
     """Caller-owned field storage: 15 or 20 planes by layout (see include/ah.h), shape
-    (planes, nz, ny, nx)."""
-    return torch.empty((p.planes, p.nz, p.ny, p.nx), dtype=p.dtype, device=device)
+    (planes, nz + 2 z_halo, ny, nx)."""
+    return torch.empty((p.planes, p.nz_stored, p.ny, p.nx), dtype=p.dtype, device=device)
 
 
 def _check(lib, ctx, rc):
@@ -251,7 +259,7 @@ class Context:
         maps, off = [], 0
         for p in self.params:
             n = 3 * p.sites
-            maps.append(wmap[off:off + n].view(3, p.nz, p.ny, p.nx))
+            maps.append(wmap[off:off + n].view(3, p.nz_stored, p.ny, p.nx))
             off += n
         return obs, maps
 
@@ -273,7 +281,8 @@ class Context:
         return n.value
 
     def fields(self, r: int = 0) -> torch.Tensor:
-        """The current state S_n of realization r as a (10, nz, ny, nx) tensor (a copy)."""
+        """The current state S_n of realization r as a (10, nz + 2 z_halo, ny, nx) tensor (a
+        copy)."""
         idx = torch.tensor(self.current_planes(r), device=self.planes[r].device)
         return self.planes[r].index_select(0, idx)
 

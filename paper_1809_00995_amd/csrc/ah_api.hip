@@ -27,6 +27,7 @@ struct ah_ctx {
     int nreal = 0;
     int prec = AH_FP64;
     int layout = AH_LAYOUT_15;
+    int zh = 0;                       // z_halo of every realization
     hipStream_t stream = nullptr;
     std::vector<ah_params> p;
     std::vector<int64_t> step;        // host mirror of each realization's step index
@@ -99,7 +100,8 @@ int grid_for(int64_t n, int threads, int cap) {
     return (int)(b < cap ? (b < 1 ? 1 : b) : cap);
 }
 
-int64_t sites_of(const ah_params &q) { return (int64_t)q.nx * q.ny * q.nz; }
+// Stored sites per plane: nx*ny*nz, plus the halo planes of a slab.
+int64_t sites_of(const ah_params &q) { return (int64_t)q.nx * q.ny * (q.nz + 2 * q.z_halo); }
 
 double scale_factor_host(const ah_params &p, double tau) {
     double t = tau > 0.0 ? tau : 0.0;
@@ -112,8 +114,14 @@ int validate(const ah_params &q, int r, const ah_buffers &b, int prec, int layou
     };
     if (q.nx < 4 || q.ny < 4 || q.nz < 4)
         return bad(AH_E_INVALID, "extents must be >= 4");
-    if ((int64_t)q.nx * q.ny * q.nz >= (int64_t)1 << 31)
-        return bad(AH_E_INVALID, "nx*ny*nz must be < 2^31");
+    if (q.z_halo < 0 || q.z_halo > 2 || q.reserved != 0)
+        return bad(AH_E_INVALID, "z_halo must be 0, 1 or 2 and reserved 0");
+    if (sites_of(q) >= (int64_t)1 << 31)
+        return bad(AH_E_INVALID, "nx*ny*(nz + 2 z_halo) must be < 2^31");
+    if (q.z_halo > 0 && q.nx % 64 != 0)
+        return bad(AH_E_INVALID, "a slab (z_halo > 0) needs the tiled kernels: nx % 64 == 0");
+    if (q.z_halo > 0 && q.init != AH_INIT_NONE && q.init != AH_INIT_VACUUM)
+        return bad(AH_E_INVALID, "a slab (z_halo > 0) takes AH_INIT_NONE or AH_INIT_VACUUM");
     if (q.precision != prec)
         return bad(AH_E_INVALID, "all realizations must share one precision");
     if (q.precision != AH_FP64 && q.precision != AH_FP32)
@@ -409,7 +417,7 @@ int launch_pass(ah_ctx *c, int steps, Slot *slots_row, const char *want_meas, bo
                 continue;
             const ah_params &q = c->p[r];
             int rc = launch_step_tiled2(c->prec == AH_FP64, c->d_desc, c->d_coef, r, c->nreal, q.nx,
-                                        q.ny, q.nz, c->tile_y2, c->cz2[r], c->stream);
+                                        q.ny, q.nz, q.z_halo, c->tile_y2, c->cz2[r], c->stream);
             if (rc)
                 return fail(c, AH_E_HIP, "two-step kernel launch failed: %s",
                             hipGetErrorString((hipError_t)rc));
@@ -559,8 +567,11 @@ int ah_init(ah_ctx **out, int32_t n_real, const ah_params *p, const ah_buffers *
     *out = nullptr;
     if (n_real < 1 || !p || !buf)
         return fail(nullptr, AH_E_INVALID, "need n_real >= 1 and non-NULL params and buffers");
-    for (int r = 0; r < n_real; ++r)
+    for (int r = 0; r < n_real; ++r) {
         TRY(validate(p[r], r, buf[r], p[0].precision, p[0].layout));
+        if (p[r].z_halo != p[0].z_halo)
+            return fail(nullptr, AH_E_INVALID, "all realizations must share one z_halo");
+    }
 
     ah_ctx *c = new (std::nothrow) ah_ctx;
     if (!c)
@@ -568,6 +579,7 @@ int ah_init(ah_ctx **out, int32_t n_real, const ah_params *p, const ah_buffers *
     c->nreal = n_real;
     c->prec = p[0].precision;
     c->layout = p[0].layout;
+    c->zh = p[0].z_halo;
     c->stream = (hipStream_t)hip_stream;
     c->p.assign(p, p + n_real);
     c->step.resize(n_real);
@@ -585,7 +597,7 @@ int ah_init(ah_ctx **out, int32_t n_real, const ah_params *p, const ah_buffers *
         d.nz = q.nz;
         d.elem = c->prec == AH_FP64 ? 8 : 4;
         d.layout = q.layout;
-        d.pad = 0;
+        d.zh = q.z_halo;
         d.N = sites_of(q);
         d.dx = q.dx;
         d.dt = q.dt;
@@ -691,9 +703,28 @@ int ah_step(ah_ctx *c, int64_t nsteps, int32_t measure_every, ah_obs *out, int64
             TRY(launch_zero(c, c->d_slots, meas.size() * c->nreal * sizeof(Slot)));
     }
 
+    // a slab with one halo plane a side cannot take pairs
+    const bool two = use_tiled2(c) && c->zh != 1;
+    if (c->zh > 0) {
+        // slabs: the caller refreshes the halo between passes, so one per call
+        int64_t passes = 0, j = 0;
+        size_t nm = 0;
+        while (j < nsteps) {
+            const bool measured = nm < meas.size() && meas_at[nm] == j;
+            const int64_t stop = nm < meas.size() ? meas_at[nm] : nsteps;
+            const int64_t adv = measured ? 1 : (two && stop - j >= 2 ? 2 : 1);
+            nm += measured ? 1 : 0;
+            j += adv;
+            ++passes;
+        }
+        if (passes > 1)
+            return fail(c, AH_E_INVALID,
+                        "a slab context advances one pass per call (%lld steps need %lld)",
+                        (long long)nsteps, (long long)passes);
+    }
+
     size_t next = 0;
     int64_t i = 0;
-    const bool two = use_tiled2(c);
     while (i < nsteps) {
         if (next < meas.size() && meas_at[next] == i) {
             // measured states take a single-step pass with the fused measurement
@@ -766,6 +797,8 @@ int ah_gauss_residual(ah_ctx *c, double *max_abs, double *rms) {
     c->err.clear();
     if (!max_abs || !rms)
         return fail(c, AH_E_INVALID, "NULL output");
+    if (c->zh > 0)
+        return fail(c, AH_E_INVALID, "the Gauss residual is not available for slabs");
     TRY(launch_zero(c, c->d_gauss, c->nreal * 2 * sizeof(unsigned long long)));
     TRY(launch_bookkeep(c, 0));
     for (int r = 0; r < c->nreal; ++r) {
@@ -818,7 +851,8 @@ int ah_set_kernel(ah_ctx *c, int32_t kernel, int32_t tile_y, int32_t chunk_z) {
         return fail(c, AH_E_INVALID, "chunk_z must be >= 0");
     if (kernel == AH_KERNEL_TILED2) {
         if (tile_y != 0 && !tiled2_ty_valid(fp64, tile_y))
-            return fail(c, AH_E_INVALID, "two-step kernel: tile_y must be 0, 4 (or 8 for FP32)");
+            return fail(c, AH_E_INVALID,
+                        "two-step kernel: tile_y must be 0, 4, 8 or 9 (FP32), 0, 4 or 5 (FP64)");
         if (c->layout != AH_LAYOUT_20)
             return fail(c, AH_E_INVALID, "two-step kernel needs AH_LAYOUT_20");
     } else if (tile_y != 0 && !tiled_ty_valid(fp64, tile_y)) {
@@ -826,6 +860,8 @@ int ah_set_kernel(ah_ctx *c, int32_t kernel, int32_t tile_y, int32_t chunk_z) {
     }
     if ((kernel == AH_KERNEL_TILED || kernel == AH_KERNEL_TILED2) && !tiled_ok(c))
         return fail(c, AH_E_INVALID, "tiled kernel needs nx %% 64 == 0");
+    if (kernel == AH_KERNEL_PLAIN && c->zh > 0)
+        return fail(c, AH_E_INVALID, "slabs (z_halo > 0) need the tiled kernels");
     c->kernel = kernel;
     const bool two = kernel == AH_KERNEL_TILED2;
     c->tile_y = two ? 0 : tile_y;
@@ -842,6 +878,8 @@ int ah_set_launch(ah_ctx *c, int32_t batched, int32_t graph_steps) {
     c->err.clear();
     if ((batched != 0 && batched != 1) || graph_steps < 0 || graph_steps > 4096)
         return fail(c, AH_E_INVALID, "batched must be 0 or 1 and graph_steps in 0..4096");
+    if (c->zh > 0 && (batched != 0 || graph_steps != 0))
+        return fail(c, AH_E_INVALID, "slabs (z_halo > 0) run unbatched without graphs");
     c->batched = batched;
     c->graph_steps = graph_steps;
     invalidate_plans(c);
@@ -854,6 +892,8 @@ int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
     c->err.clear();
     if (c->kernel == AH_KERNEL_PLAIN || !tiled_ok(c))
         return fail(c, AH_E_STATE, "autotuning needs the tiled kernel (nx %% 64 == 0)");
+    if (c->zh > 0)
+        return fail(c, AH_E_STATE, "autotuning is not available for slabs");
     const bool fp64 = c->prec == AH_FP64;
     // the kernel that runs the unmeasured steps
     const bool two = use_tiled2(c);
@@ -953,7 +993,7 @@ int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
                         if (k == 1)
                             hip_ok(hipEventRecord(e0, c->stream), "hipEventRecord");
                         hip_ok((hipError_t)(two ? launch_step_tiled2(fp64, d_desc, d_coef, 0, 1,
-                                                                     sh.nx, sh.ny, nzs, t, z,
+                                                                     sh.nx, sh.ny, nzs, 0, t, z,
                                                                      c->stream)
                                                  : launch_step_tiled(fp64, MODE_STEP, d_desc, d_coef,
                                                                      0, sh.nx, sh.ny, nzs, t, z,

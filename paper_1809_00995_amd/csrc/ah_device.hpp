@@ -26,8 +26,8 @@ struct RealDesc {
     int32_t nx, ny, nz;
     int32_t elem;          // bytes per element (4 or 8)
     int32_t layout;        // AH_LAYOUT_15 or AH_LAYOUT_20
-    int32_t pad;
-    int64_t N;             // nx * ny * nz
+    int32_t zh;            // 0: periodic in z; > 0: a slab with zh halo planes a side
+    int64_t N;             // elements per plane: nx * ny * (nz + 2 zh)
     double dx, dt, tau0, tau_ref, era_p, s, lambda0, e0, sigma;
     int64_t step0, n_end;
     double s_late, tau_s;  // s(tau) = s_late from tau_s on when tau_s > 0
@@ -93,6 +93,14 @@ __host__ __device__ __forceinline__ int field_plane(int f, int parity, int layou
     if (f >= 4 && f < 7)
         return P_AX2 + (f - 4);
     return f;
+}
+
+// Stored z-plane of slab-relative plane z (-zh <= z < nz + zh for a slab,
+// any z within one period of [0, nz) for a periodic lattice).
+__device__ __forceinline__ int zmap(const RealDesc &d, int z) {
+    if (d.zh)
+        return z + d.zh;
+    return z < 0 ? z + d.nz : (z >= d.nz ? z - d.nz : z);
 }
 
 __host__ __device__ __forceinline__ int plane_count(int layout) {

@@ -222,7 +222,7 @@ __global__ void k_finalize(const RealDesc *descs, const Slot *slots, ah_obs *out
     const Slot &sl = slots[k];
     ah_obs o;
     const double dv = d.dx * d.dx * d.dx;
-    const double vbox = (double)d.N * dv;
+    const double vbox = (double)d.nx * (double)d.ny * (double)d.nz * dv;   // the slab only
     o.step = sl.measured ? sl.c.n : -1;
     o.tau = sl.c.tau;
     o.a = sl.c.a_0;

@@ -454,15 +454,16 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
     };
     auto own = [&](int z) { return gx + nx * (gy + ny * z); };
 
-    // prologue: planes z0-1 (buffer 1) and z0 (buffer 0)
-    const int zm0 = z0 == 0 ? nz - 1 : z0 - 1;
+    // prologue: planes z0-1 (buffer 1) and z0 (buffer 0); z below is
+    // slab-relative, zmap gives the stored plane
+    const int zm0 = zmap(d, z0 - 1), zc0 = zmap(d, z0);
     SiteV<T> prv, cur, nxt;
     load_site(own(zm0), prv);
     put(1, q, prv);
     stage_halo(1, zm0);
-    load_site(own(z0), cur);
+    load_site(own(zc0), cur);
     put(0, q, cur);
-    stage_halo(0, z0);
+    stage_halo(0, zc0);
     __syncthreads();
     // yz and zx plaquettes of plane z0-1 at this column
     T pyz_m = plaq_sin(prv.uyc, prv.uys, lds[1][Q_UZC][q + G::W], lds[1][Q_UZS][q + G::W],
@@ -474,8 +475,8 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
 
     for (int z = z0; z < z1; ++z) {
         const int cb = (z - z0) & 1, nb_ = cb ^ 1;
-        const int zp = z + 1 == nz ? 0 : z + 1;
-        const int s = own(z);
+        const int zp = zmap(d, z + 1);
+        const int s = own(zmap(d, z));
         // the momenta are read once, by this thread only: streaming loads
         const T pr0 = __builtin_nontemporal_load(pir + s), pi0 = __builtin_nontemporal_load(pii + s);
         const T ex0 = __builtin_nontemporal_load(E0 + s), ey0 = __builtin_nontemporal_load(E1 + s);

@@ -261,7 +261,9 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
     const StepK<T> K0 = step_k<T>(d, c0), K1 = step_k<T>(d, c1);
 
     auto own_site = [&](int z) { return gx + nx * (gy + ny * z); };
-    auto zwrap = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
+    // z below is slab-relative; zmap gives the stored plane (periodic wrap,
+    // or the offset past the halo planes of a slab)
+    auto zwrap = [&](int z) { return zmap(d, z); };
     // element s of field f of S_n, and the store of the new state
     auto LD = [&](int f, int s) -> T {
         if constexpr (OFF32)
@@ -380,7 +382,7 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
     const int nk = (z1 - z0) + 2;
     auto body = [&](auto cbc, int k, SnSet &cur, SnSet &nxt, S1Set &c1, S1Set &n1) {
         constexpr int CB = decltype(cbc)::value, NB = CB ^ 1;
-        const int zs = zwrap(z0 - 1 + k);
+        const int zi = z0 - 1 + k, zs = zwrap(zi);
         // (a) stage S_n at zs+1 from the prefetched values; start the next reads
         const T pr0 = f_pr0, pi0 = f_pi0, ex0 = f_ex0, ey0 = f_ey0, ez0 = f_ez0;
         // and form the forward plaquettes of plane zs (complete since the last
@@ -454,7 +456,7 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
                                                               c1.v.ey, c1.v.ez, fp1);
                 const SiteNew<T> n2 = leapfrog_site(st, K1);
                 if (owner)
-                    store_state(n2, own_site(zwrap(zs - 1)));
+                    store_state(n2, own_site(zwrap(zi - 1)));
             }
             if (k >= 1) {
                 // plane zs-1 is below the next plane of step two
@@ -564,9 +566,9 @@ inline bool fits_off32(long n_sites, int elem) {
 
 template <typename T, int TY>
 hipError_t launch_tiled2_ty(const RealDesc *desc, const Coef *coef, int r, int nreal, int nx, int ny,
-                            int nz, int cz, hipStream_t stream) {
+                            int nz, int zh, int cz, hipStream_t stream) {
     const long blocks = (long)(nx / 64) * ((ny + TY - 1) / TY) * ((nz + cz - 1) / cz);
-    if (fits_off32((long)nx * ny * nz, sizeof(T)))
+    if (fits_off32((long)nx * ny * (nz + 2 * zh), sizeof(T)))
         hipLaunchKernelGGL((k_step_tiled2<T, TY, true>), dim3((unsigned)blocks),
                            dim3(64 * Tile2Geom<TY>::NW), 0, stream, desc, coef, r, nreal, cz);
     else
@@ -575,24 +577,26 @@ hipError_t launch_tiled2_ty(const RealDesc *desc, const Coef *coef, int r, int n
     return hipGetLastError();
 }
 
-// Launch the two-step kernel for realization r (nx % 64 == 0, 20-plane layout).
+// Launch the two-step kernel for realization r (nx % 64 == 0, 20-plane layout;
+// nz planes advanced, zh halo planes a side for a slab).
 inline int launch_step_tiled2(bool fp64, const RealDesc *desc, const Coef *coef, int r, int nreal,
-                              int nx, int ny, int nz, int tile_y, int chunk_z, hipStream_t stream) {
+                              int nx, int ny, int nz, int zh, int tile_y, int chunk_z,
+                              hipStream_t stream) {
     int ty = tile_y, cz = chunk_z;
     tiled2_defaults(fp64, nx, ny, nz, ty, cz);
     if (nx % 64 != 0 || !tiled2_ty_valid(fp64, ty) || cz < 1)
         return (int)hipErrorInvalidValue;
     hipError_t e;
     if (fp64 && ty == 5)
-        e = launch_tiled2_ty<double, 5>(desc, coef, r, nreal, nx, ny, nz, cz, stream);
+        e = launch_tiled2_ty<double, 5>(desc, coef, r, nreal, nx, ny, nz, zh, cz, stream);
     else if (fp64)
-        e = launch_tiled2_ty<double, 4>(desc, coef, r, nreal, nx, ny, nz, cz, stream);
+        e = launch_tiled2_ty<double, 4>(desc, coef, r, nreal, nx, ny, nz, zh, cz, stream);
     else if (ty == 4)
-        e = launch_tiled2_ty<float, 4>(desc, coef, r, nreal, nx, ny, nz, cz, stream);
+        e = launch_tiled2_ty<float, 4>(desc, coef, r, nreal, nx, ny, nz, zh, cz, stream);
     else if (ty == 9)
-        e = launch_tiled2_ty<float, 9>(desc, coef, r, nreal, nx, ny, nz, cz, stream);
+        e = launch_tiled2_ty<float, 9>(desc, coef, r, nreal, nx, ny, nz, zh, cz, stream);
     else
-        e = launch_tiled2_ty<float, 8>(desc, coef, r, nreal, nx, ny, nz, cz, stream);
+        e = launch_tiled2_ty<float, 8>(desc, coef, r, nreal, nx, ny, nz, zh, cz, stream);
     return (int)e;
 }
 

@@ -100,6 +100,38 @@ def test_bad_extents_alignment_and_null():
     assert lib.ah_error_string(B.AH_E_NONFINITE) == b"non-finite field values"
 
 
+def test_slab_parameters_are_validated():
+    """z_halo (a z-slab of a larger lattice) must be 0, 1 or 2 with reserved 0, shared by
+    every realization, and a slab needs nx % 64 == 0 and AH_INIT_NONE or AH_INIT_VACUUM;
+    all refused before any device work."""
+    lib = AH.load_library()
+    ctx = C.c_void_p()
+    b = B._Buffers(4096)
+    none = dict(init=AH.AH_INIT_NONE)
+
+    def init(*ps):
+        arr = (B._Params * len(ps))(*[q._c() for q in ps])
+        bufs = (B._Buffers * len(ps))(*[B._Buffers(4096 * (k + 1)) for k in range(len(ps))])
+        return lib.ah_init(C.byref(ctx), len(ps), arr, bufs, None)
+
+    assert init(AH.Params(64, 8, 8, z_halo=3, **none)) == B.AH_E_INVALID
+    assert "z_halo" in lib.ah_last_error(None).decode()
+    assert init(AH.Params(64, 8, 8, z_halo=-1, **none)) == B.AH_E_INVALID
+    bad = AH.Params(64, 8, 8, z_halo=2, **none)._c()
+    bad.reserved = 1
+    assert lib.ah_init(C.byref(ctx), 1, C.byref(bad), C.byref(b), None) == B.AH_E_INVALID
+    assert init(AH.Params(32, 8, 8, z_halo=2, **none)) == B.AH_E_INVALID
+    assert "nx % 64" in lib.ah_last_error(None).decode()
+    assert init(AH.Params(64, 8, 8, z_halo=2)) == B.AH_E_INVALID   # random-phase start
+    assert "AH_INIT_NONE" in lib.ah_last_error(None).decode()
+    assert init(AH.Params(64, 8, 8, z_halo=2, **none), AH.Params(64, 8, 8, **none)) == \
+        B.AH_E_INVALID
+    assert "one z_halo" in lib.ah_last_error(None).decode()
+    # stored sites include the halo planes
+    q = AH.Params(64, 8, 8, z_halo=2)
+    assert q.nz_stored == 12 and q.sites == 64 * 8 * 12
+
+
 def test_bench_refuses_more_than_one_gpu():
     """bench.py measures one GPU; --gpus N > 1 exits with a message before touching a GPU."""
     import sys
