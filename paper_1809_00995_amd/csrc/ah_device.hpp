@@ -96,11 +96,12 @@ __host__ __device__ __forceinline__ int field_plane(int f, int parity, int layou
 }
 
 // Stored z-plane of slab-relative plane z (-zh <= z < nz + zh for a slab,
-// any z within one period of [0, nz) for a periodic lattice).
+// any z within one period of [0, nz) for a periodic lattice, zh = 0).  One
+// expression for both, so that the compiler emits selects, not branches: a
+// slab's planes never leave [0, nz + 2 zh).
 __device__ __forceinline__ int zmap(const RealDesc &d, int z) {
-    if (d.zh)
-        return z + d.zh;
-    return z < 0 ? z + d.nz : (z >= d.nz ? z - d.nz : z);
+    const int w = z + d.zh, top = d.nz + 2 * d.zh;
+    return w < 0 ? w + d.nz : (w >= top ? w - d.nz : w);
 }
 
 __host__ __device__ __forceinline__ int plane_count(int layout) {
