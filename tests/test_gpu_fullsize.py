@@ -4,6 +4,9 @@
   evaluated site by site on sampled sites (tile edges in x and y, z-chunk
   edges, lattice boundaries, random interior sites), FP32 and FP64; and the
   two-steps-per-pass kernel against single steps, bit for bit.
+- 1024 x 1024 x 128 (one GPU's share of 1024^3 over 8 GPUs, bench.py's slab
+  form): the slab with halo planes closed on itself against the periodic
+  lattice, bit for bit.
 - 256^3 radiation era, s = 1, to tau = 64 (640 steps, diagnostics every 10):
   fields after 10 steps against the oracle (FP64: 1e-12; FP32 from the
   FP32-rounded start: 1e-5 per field group), diagnostics at step 10 against
@@ -106,6 +109,45 @@ def test_planes_above_4gib_two_step_pass():
         del planes
         torch.cuda.empty_cache()
     assert torch.equal(runs[0], runs[1])
+
+
+def test_slab_1024x1024x128_equals_periodic():
+    """One GPU's share of 1024^3 over 8 GPUs, as bench.py times it: a 1024 x 1024 x 128
+    FP32 slab with two halo planes a side, refilled before every pass from its own faces,
+    equals the periodic 1024 x 1024 x 128 lattice bit for bit through pairs, a fused
+    measured step and a single step (the periodic kernels are pinned to the oracle above)."""
+    print("CASE test=slab_1024", flush=True)
+    nxy, nz, H = 1024, 128, 2
+    base = dict(precision=AH.AH_FP32, dx=0.5, dt=0.1, tau0=1.0, tau_ref=256.0, era_p=1.0,
+                s=1.0, layout=AH.AH_LAYOUT_20)
+    pp = AH.Params(nxy, nxy, nz, seed=99, **base)
+    ps = AH.Params(nxy, nxy, nz, init=AH.AH_INIT_NONE, z_halo=H, **base)
+    tp, ts = AH.alloc_planes(pp), AH.alloc_planes(ps)
+    with AH.Context([pp], [tp]) as ref:
+        ts.zero_()
+        ts[:10, H:H + nz] = ref.fields()
+        with AH.Context([ps], [ts]) as slab:
+            def refill():
+                c0 = slab.current_planes(0)[0]
+                cur = ts[c0:c0 + 10]
+                cur[:, :H] = cur[:, nz:nz + H]
+                cur[:, H + nz:] = cur[:, H:2 * H]
+            refill()
+            for k, meas in ((2, 0), (1, 1), (1, 0), (2, 0)):
+                if meas:
+                    (g,), = ref.step(k, measure_every=1)
+                    (h,), = slab.step(k, measure_every=1)
+                    assert h.n_wind_dir == g.n_wind_dir and h.n_pierced == g.n_pierced
+                    assert h.energy == pytest.approx(g.energy, rel=1e-12)
+                    assert h.v2[0] == pytest.approx(g.v2[0], rel=1e-10)
+                else:
+                    ref.step(k)
+                    slab.step(k)
+                refill()
+            assert slab.current_step() == ref.current_step() == 6
+            assert torch.equal(slab.fields()[:, H:H + nz], ref.fields())
+    del tp, ts
+    torch.cuda.empty_cache()
 
 
 def test_config_256cubed_radiation_run(O):
