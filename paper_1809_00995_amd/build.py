@@ -1,8 +1,16 @@
 """Build ``libah.so`` (the gfx950 HIP library behind include/ah.h) in-tree.
 
-Runs ``hipcc --offload-arch=gfx950`` on the single translation unit
-``csrc/ah_api.hip``.  Packed-FP32 instruction selection is switched off for
-the device code (``-Xclang -target-feature -Xclang -packed-fp32-ops``).
+Runs ``hipcc --offload-arch=gfx950`` on three translation units -- the C ABI
+with every other kernel (``csrc/ah_api.hip``) and the FP32 and FP64
+two-steps-per-pass kernels (``csrc/k_step_tiled2_f32.hip``,
+``csrc/k_step_tiled2_f64.hip``) -- in parallel, then links them.
+Packed-FP32 instruction selection is switched off for all device code
+(``-Xclang -target-feature -Xclang -packed-fp32-ops``).  The FP32 two-step
+kernels alone take the instruction-level-parallelism machine scheduler
+(``-mllvm -amdgpu-sched-strategy=max-ilp``): measured on one GPU against the
+default, their pairs run 2.4 % faster, while the single-step kernels would
+lose occupancy to it (VGPRs 95 -> 130 in the batched one, 5 -> 3 waves per
+SIMD) and the FP64 pairs run 0.8 % slower.
 """
 from __future__ import annotations
 
@@ -12,7 +20,11 @@ import subprocess
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = os.path.join(PKG, "csrc", "ah_api.hip")
+CSRC = os.path.join(PKG, "csrc")
+# translation unit -> extra hipcc options
+UNITS = [("ah_api.hip", []),
+         ("k_step_tiled2_f32.hip", ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]),
+         ("k_step_tiled2_f64.hip", [])]
 LIB = os.path.join(PKG, "libah.so")
 ARCH = "gfx950"
 
@@ -25,15 +37,28 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Wall", "-Wno-unused-function",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
-           "-o", LIB + ".tmp", SRC]
+    common = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+              "-Wall", "-Wno-unused-function",
+              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+              "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    objs, procs = [], []
+    for src, extra in UNITS:
+        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
+        cmd = common + extra + ["-c", "-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), src))
+        objs.append(obj)
+    failed = [src for p, src in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, "hipcc " + " ".join(failed))
+    link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
     os.replace(LIB + ".tmp", LIB)
+    for obj in objs:
+        os.remove(obj)
     return LIB
 
 

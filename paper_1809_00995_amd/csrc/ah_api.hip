@@ -18,8 +18,8 @@
 #include "k_common.hpp"
 #include "k_measure.hpp"
 #include "k_step_plain.hpp"
-#include "k_step_tiled.hpp"
-#include "k_step_tiled2.hpp"
+#include "k_step_tiled_launch.hpp"
+#include "k_step_tiled2_api.hpp"
 
 using namespace ah;
 

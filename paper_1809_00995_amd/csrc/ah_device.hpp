@@ -33,6 +33,12 @@ struct RealDesc {
     double s_late, tau_s;  // s(tau) = s_late from tau_s on when tau_s > 0
 };
 
+// A work item of the batched kernels: tile `tile` of realization r, with that
+// realization's z-chunk cz.
+struct BatchItem {
+    int32_t r, tile, cz, pad;
+};
+
 // FP64 bookkeeping for advancing realization r from S_n (written on the
 // device by k_bookkeep before each step or measurement).
 struct Coef {

@@ -35,6 +35,7 @@
 #include <type_traits>
 
 #include "k_step_tiled.hpp"
+#include "k_step_tiled2_api.hpp"
 
 namespace ah {
 
@@ -518,52 +519,6 @@ k_step_batch2(const RealDesc *descs, const Coef *coefs, const BatchItem *items, 
     }
 }
 
-// Tile heights of the two-step kernel.  LDS per block: FP32 112 KB at TY = 8,
-// 122 KB at TY = 9; FP64 143 KB at TY = 4, 163 KB at TY = 5 (a workgroup may
-// hold up to 160 KiB on gfx950).  TY = 9 (FP32) and TY = 5 (FP64) give 12 and
-// 8 wavefronts, an equal number on each of a CU's four SIMDs.
-inline bool tiled2_ty_valid(bool fp64, int ty) {
-    return fp64 ? (ty == 4 || ty == 5) : (ty == 4 || ty == 8 || ty == 9);
-}
-
-// Default tile height for lattices with the given y extents (weights: sites
-// per unit of y): the balanced height (9 FP32, 5 FP64) unless its ragged last
-// rows of tiles idle more than 2 % of the sites beyond the smaller height's.
-inline int tiled2_default_ty(bool fp64, const int *ny, const long *weight, int n) {
-    const int big = fp64 ? 5 : 9, small = big - 1;
-    double pad_big = 0, pad_small = 0, total = 0;
-    for (int i = 0; i < n; ++i) {
-        pad_big += (double)weight[i] * ((ny[i] + big - 1) / big * big - ny[i]);
-        pad_small += (double)weight[i] * ((ny[i] + small - 1) / small * small - ny[i]);
-        total += (double)weight[i] * ny[i];
-    }
-    return pad_big <= pad_small + 0.02 * total ? big : small;
-}
-
-inline void tiled2_defaults(bool fp64, int nx, int ny, int nz, int &ty, int &cz) {
-    if (ty <= 0) {
-        const long w = (long)nx * nz;
-        ty = tiled2_default_ty(fp64, &ny, &w, 1);
-    }
-    if (cz <= 0) {
-        // long chunks amortise the two extra planes of step one; aim at ~2048 blocks
-        const long tiles_xy = (long)(nx / 64) * ((ny + ty - 1) / ty);
-        long chunks = (2048 + tiles_xy - 1) / tiles_xy;
-        const long max_chunks = (nz + 31) / 32;
-        if (chunks > max_chunks)
-            chunks = max_chunks;
-        if (chunks < 1)
-            chunks = 1;
-        cz = (int)((nz + chunks - 1) / chunks);
-    }
-}
-
-// Whether every plane of an nx*ny*nz lattice of elem-byte values is below
-// 4 GiB (32-bit byte offsets).
-inline bool fits_off32(long n_sites, int elem) {
-    return (unsigned long long)n_sites * (unsigned long long)elem <= (1ull << 32);
-}
-
 template <typename T, int TY>
 hipError_t launch_tiled2_ty(const RealDesc *desc, const Coef *coef, int r, int nreal, int nx, int ny,
                             int nz, int zh, int cz, hipStream_t stream) {
@@ -577,26 +532,25 @@ hipError_t launch_tiled2_ty(const RealDesc *desc, const Coef *coef, int r, int n
     return hipGetLastError();
 }
 
-// Launch the two-step kernel for realization r (nx % 64 == 0, 20-plane layout;
-// nz planes advanced, zh halo planes a side for a slab).
-inline int launch_step_tiled2(bool fp64, const RealDesc *desc, const Coef *coef, int r, int nreal,
-                              int nx, int ny, int nz, int zh, int tile_y, int chunk_z,
-                              hipStream_t stream) {
-    int ty = tile_y, cz = chunk_z;
-    tiled2_defaults(fp64, nx, ny, nz, ty, cz);
-    if (nx % 64 != 0 || !tiled2_ty_valid(fp64, ty) || cz < 1)
-        return (int)hipErrorInvalidValue;
+// Launch the two-step kernel of element type T for realization r with tile
+// height ty and z-chunk cz (both resolved and checked by the caller).
+template <typename T>
+int launch_step_tiled2_t(const RealDesc *desc, const Coef *coef, int r, int nreal, int nx, int ny,
+                         int nz, int zh, int ty, int cz, hipStream_t stream) {
     hipError_t e;
-    if (fp64 && ty == 5)
-        e = launch_tiled2_ty<double, 5>(desc, coef, r, nreal, nx, ny, nz, zh, cz, stream);
-    else if (fp64)
-        e = launch_tiled2_ty<double, 4>(desc, coef, r, nreal, nx, ny, nz, zh, cz, stream);
-    else if (ty == 4)
-        e = launch_tiled2_ty<float, 4>(desc, coef, r, nreal, nx, ny, nz, zh, cz, stream);
-    else if (ty == 9)
-        e = launch_tiled2_ty<float, 9>(desc, coef, r, nreal, nx, ny, nz, zh, cz, stream);
-    else
-        e = launch_tiled2_ty<float, 8>(desc, coef, r, nreal, nx, ny, nz, zh, cz, stream);
+    if constexpr (std::is_same<T, double>::value) {
+        if (ty == 5)
+            e = launch_tiled2_ty<double, 5>(desc, coef, r, nreal, nx, ny, nz, zh, cz, stream);
+        else
+            e = launch_tiled2_ty<double, 4>(desc, coef, r, nreal, nx, ny, nz, zh, cz, stream);
+    } else {
+        if (ty == 4)
+            e = launch_tiled2_ty<float, 4>(desc, coef, r, nreal, nx, ny, nz, zh, cz, stream);
+        else if (ty == 9)
+            e = launch_tiled2_ty<float, 9>(desc, coef, r, nreal, nx, ny, nz, zh, cz, stream);
+        else
+            e = launch_tiled2_ty<float, 8>(desc, coef, r, nreal, nx, ny, nz, zh, cz, stream);
+    }
     return (int)e;
 }
 
@@ -627,28 +581,22 @@ hipError_t batch2_ty(const RealDesc *desc, const Coef *coef, const BatchItem *it
     return hipGetLastError();
 }
 
-// The batched two-step kernel: with grid_out != NULL only its resident-block
-// count (occupancy x compute units) is returned; otherwise it is launched on
-// `grid` blocks.  off32: every realization's planes are below 4 GiB.
-inline int batch2_dispatch(bool fp64, int ty, bool off32, const RealDesc *desc, const Coef *coef,
-                           const BatchItem *items, int n_items, int nreal, int grid,
-                           hipStream_t stream, int *grid_out) {
-    if (!tiled2_ty_valid(fp64, ty))
-        return (int)hipErrorInvalidValue;
-#define AH_B2(T, TY_)                                                                              \
+// The batched two-step kernel of element type T and tile height ty (checked
+// by the caller): with grid_out != NULL only its resident-block count
+// (occupancy x compute units) is returned; otherwise it is launched on `grid`
+// blocks.  off32: every realization's planes are below 4 GiB.
+template <typename T>
+int batch2_dispatch_t(int ty, bool off32, const RealDesc *desc, const Coef *coef,
+                      const BatchItem *items, int n_items, int nreal, int grid, hipStream_t stream,
+                      int *grid_out) {
+#define AH_B2(TY_)                                                                                 \
     (off32 ? batch2_ty<T, TY_, true>(desc, coef, items, n_items, nreal, grid, stream, grid_out)    \
            : batch2_ty<T, TY_, false>(desc, coef, items, n_items, nreal, grid, stream, grid_out))
     hipError_t e;
-    if (fp64 && ty == 5)
-        e = AH_B2(double, 5);
-    else if (fp64)
-        e = AH_B2(double, 4);
-    else if (ty == 4)
-        e = AH_B2(float, 4);
-    else if (ty == 9)
-        e = AH_B2(float, 9);
+    if constexpr (std::is_same<T, double>::value)
+        e = ty == 5 ? AH_B2(5) : AH_B2(4);
     else
-        e = AH_B2(float, 8);
+        e = ty == 4 ? AH_B2(4) : (ty == 9 ? AH_B2(9) : AH_B2(8));
 #undef AH_B2
     return (int)e;
 }

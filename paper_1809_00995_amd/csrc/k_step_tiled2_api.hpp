@@ -1,0 +1,107 @@
+// k_step_tiled2_api.hpp -- host interface of the two-steps-per-pass kernels
+// (k_step_tiled2.hpp): tile-height choice and the launchers.  The kernels are
+// compiled in translation units of their own, one per element type
+// (k_step_tiled2_f32.hip, k_step_tiled2_f64.hip), so that each can take the
+// code-generation options measured best for it; this header carries no device
+// code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ah_device.hpp"
+
+namespace ah {
+
+// Tile heights of the two-step kernel.  LDS per block: FP32 112 KB at TY = 8,
+// 122 KB at TY = 9; FP64 143 KB at TY = 4, 163 KB at TY = 5 (a workgroup may
+// hold up to 160 KiB on gfx950).  TY = 9 (FP32) and TY = 5 (FP64) give 12 and
+// 8 wavefronts, an equal number on each of a CU's four SIMDs.
+inline bool tiled2_ty_valid(bool fp64, int ty) {
+    return fp64 ? (ty == 4 || ty == 5) : (ty == 4 || ty == 8 || ty == 9);
+}
+
+// Default tile height for lattices with the given y extents (weights: sites
+// per unit of y): the balanced height (9 FP32, 5 FP64) unless its ragged last
+// rows of tiles idle more than 2 % of the sites beyond the smaller height's.
+inline int tiled2_default_ty(bool fp64, const int *ny, const long *weight, int n) {
+    const int big = fp64 ? 5 : 9, small = big - 1;
+    double pad_big = 0, pad_small = 0, total = 0;
+    for (int i = 0; i < n; ++i) {
+        pad_big += (double)weight[i] * ((ny[i] + big - 1) / big * big - ny[i]);
+        pad_small += (double)weight[i] * ((ny[i] + small - 1) / small * small - ny[i]);
+        total += (double)weight[i] * ny[i];
+    }
+    return pad_big <= pad_small + 0.02 * total ? big : small;
+}
+
+inline void tiled2_defaults(bool fp64, int nx, int ny, int nz, int &ty, int &cz) {
+    if (ty <= 0) {
+        const long w = (long)nx * nz;
+        ty = tiled2_default_ty(fp64, &ny, &w, 1);
+    }
+    if (cz <= 0) {
+        // long chunks amortise the two extra planes of step one; aim at ~2048 blocks
+        const long tiles_xy = (long)(nx / 64) * ((ny + ty - 1) / ty);
+        long chunks = (2048 + tiles_xy - 1) / tiles_xy;
+        const long max_chunks = (nz + 31) / 32;
+        if (chunks > max_chunks)
+            chunks = max_chunks;
+        if (chunks < 1)
+            chunks = 1;
+        cz = (int)((nz + chunks - 1) / chunks);
+    }
+}
+
+// Whether every plane of an nx*ny*nz lattice of elem-byte values is below
+// 4 GiB (32-bit byte offsets).
+inline bool fits_off32(long n_sites, int elem) {
+    return (unsigned long long)n_sites * (unsigned long long)elem <= (1ull << 32);
+}
+
+// Defined in k_step_tiled2.hpp, instantiated for float and double in their own
+// translation units.
+template <typename T>
+int launch_step_tiled2_t(const RealDesc *desc, const Coef *coef, int r, int nreal, int nx, int ny,
+                         int nz, int zh, int ty, int cz, hipStream_t stream);
+template <typename T>
+int batch2_dispatch_t(int ty, bool off32, const RealDesc *desc, const Coef *coef,
+                      const BatchItem *items, int n_items, int nreal, int grid, hipStream_t stream,
+                      int *grid_out);
+extern template int launch_step_tiled2_t<float>(const RealDesc *, const Coef *, int, int, int, int,
+                                                int, int, int, int, hipStream_t);
+extern template int launch_step_tiled2_t<double>(const RealDesc *, const Coef *, int, int, int,
+                                                 int, int, int, int, int, hipStream_t);
+extern template int batch2_dispatch_t<float>(int, bool, const RealDesc *, const Coef *,
+                                             const BatchItem *, int, int, int, hipStream_t, int *);
+extern template int batch2_dispatch_t<double>(int, bool, const RealDesc *, const Coef *,
+                                              const BatchItem *, int, int, int, hipStream_t, int *);
+
+// Launch the two-step kernel for realization r (nx % 64 == 0, 20-plane layout;
+// nz planes advanced, zh halo planes a side for a slab); tile_y, chunk_z 0
+// pick the defaults.
+inline int launch_step_tiled2(bool fp64, const RealDesc *desc, const Coef *coef, int r, int nreal,
+                              int nx, int ny, int nz, int zh, int tile_y, int chunk_z,
+                              hipStream_t stream) {
+    int ty = tile_y, cz = chunk_z;
+    tiled2_defaults(fp64, nx, ny, nz, ty, cz);
+    if (nx % 64 != 0 || !tiled2_ty_valid(fp64, ty) || cz < 1)
+        return (int)hipErrorInvalidValue;
+    return fp64 ? launch_step_tiled2_t<double>(desc, coef, r, nreal, nx, ny, nz, zh, ty, cz, stream)
+                : launch_step_tiled2_t<float>(desc, coef, r, nreal, nx, ny, nz, zh, ty, cz, stream);
+}
+
+// The batched two-step kernel: with grid_out != NULL only its resident-block
+// count (occupancy x compute units) is returned; otherwise it is launched on
+// `grid` blocks.  off32: every realization's planes are below 4 GiB.
+inline int batch2_dispatch(bool fp64, int ty, bool off32, const RealDesc *desc, const Coef *coef,
+                           const BatchItem *items, int n_items, int nreal, int grid,
+                           hipStream_t stream, int *grid_out) {
+    if (!tiled2_ty_valid(fp64, ty))
+        return (int)hipErrorInvalidValue;
+    return fp64 ? batch2_dispatch_t<double>(ty, off32, desc, coef, items, n_items, nreal, grid,
+                                            stream, grid_out)
+                : batch2_dispatch_t<float>(ty, off32, desc, coef, items, n_items, nreal, grid,
+                                           stream, grid_out);
+}
+
+} // namespace ah
