@@ -723,10 +723,25 @@ int ah_step(ah_ctx *c, int64_t nsteps, int32_t measure_every, ah_obs *out, int64
                         (long long)nsteps, (long long)passes);
     }
 
+    // FP32 with pairs: a measured state whose next stop is an even number of
+    // steps away is measured by a read-only pass and then stepped in pairs
+    // (at 512^3: 2.8 + 2.7 ms against 3.7 + 2.1 ms for the fused measuring step
+    // and the odd single step that would follow); FP64 pairs cost more than
+    // that saves, and slabs and batched launches keep the fused step.
+    const bool ro_measure = two && c->prec == AH_FP32 && c->zh == 0 && !batch_ok(c);
     size_t next = 0;
     int64_t i = 0;
     while (i < nsteps) {
         if (next < meas.size() && meas_at[next] == i) {
+            const int64_t stop = next + 1 < meas.size() ? meas_at[next + 1] : nsteps;
+            if (ro_measure && (stop - i) % 2 == 0) {
+                TRY(launch_bookkeep(c, 0));
+                for (int r = 0; r < c->nreal; ++r)
+                    if (meas[next][r])
+                        TRY(launch_measure(c, r, c->d_slots + next * c->nreal + r, nullptr));
+                ++next;
+                continue;   // the steps from i go in pairs
+            }
             // measured states take a single-step pass with the fused measurement
             TRY(launch_pass(c, 1, c->d_slots + next * c->nreal, meas[next].data(), true));
             mirror_pass(c, 1);
