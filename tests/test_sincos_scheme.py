@@ -1,4 +1,5 @@
-"""The device sin/cos of the link phasors (ah_device.hpp), checked on the CPU.
+"""The device sin/cos of the link phasors and the FP32 phase of the winding filter
+(ah_device.hpp), checked on the CPU.
 
 The constants are read from the header and the scheme (reduction by multiples
 of pi in two fused multiply-adds, odd and even minimax polynomials, sign flip
@@ -117,3 +118,71 @@ def test_double_sincos_within_stated_error():
         worst = max(worst, abs(M(s) - mp.sin(M(x))), abs(M(co) - mp.cos(M(x))))
     # a few units of 2^-53 on results of magnitude up to 1
     assert worst < 4 * 2.0 ** -53, float(worst)
+
+
+def _phase_constants():
+    src = open(HDR).read()
+    start = src.index("float phase_f32(float y, float x")
+    body = src[src.index("{", start):src.index("\n}\n", start)]
+    # floating literals with a point or an exponent (the guards are 1e-30f, 3.0e38f)
+    lit = re.compile(r"[-+]?\d+(?:\.\d*)?e[-+]?\d+f?|[-+]?\d+\.\d*f?")
+    vals = [float(v.rstrip("f")) for v in lit.findall(body)]
+    # T (highest power first, 7 terms), pi/2, pi, the 1e-30 and 3e38 guards
+    return vals[:7], vals[7], vals[8], vals[9], vals[10]
+
+
+def _phase_f32(y, x, consts, rcp_ulp=0):
+    T, half_pi, pi, lo, hi = consts
+    f32 = np.float32
+
+    def fma(a, b, c):
+        return (np.asarray(a, np.float64) * np.asarray(b, np.float64)
+                + np.asarray(c, np.float64)).astype(f32)
+
+    ax, ay = np.abs(x), np.abs(y)
+    mx, mn = np.maximum(ax, ay), np.minimum(ax, ay)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rc = (1.0 / mx.astype(np.float64)).astype(f32)
+    if rcp_ulp:
+        rc = np.nextafter(rc, np.float32(np.inf) if rcp_ulp > 0 else np.float32(0))
+    with np.errstate(invalid="ignore", over="ignore"):
+        a = (mn * rc).astype(f32)
+        u = (a * a).astype(f32)
+        t = fma(u, T[0], T[1])
+        for cf in T[2:]:
+            t = fma(u, t, cf)
+        r = fma((a * u).astype(f32), t, a)
+    r = np.where(ay > ax, (f32(half_pi) - r).astype(f32), r)
+    r = np.where(np.signbit(x), (f32(pi) - r).astype(f32), r)
+    r = np.copysign(r, y)
+    return np.where((mx >= f32(lo)) & (mx <= f32(hi)), r, np.float32(np.nan))
+
+
+def test_phase_f32_within_stated_error_and_conventions():
+    """The FP32 phase of the winding filter: below 5e-7 from atan2 for every octant
+    over 40 decades of magnitude (with the hardware reciprocal one ulp either way),
+    atan2's signed-zero conventions, and NaN below 1e-30 or beyond the float range
+    (where the measuring kernels fall back to FP64 phases)."""
+    consts = _phase_constants()
+    assert len(consts[0]) == 7
+    rng = np.random.default_rng(7)
+    m = 10.0 ** rng.uniform(-20, 20, 600_000)
+    ang = rng.uniform(-np.pi, np.pi, m.size)
+    ang[:100_000] = np.round(ang[:100_000] / (np.pi / 4)) * (np.pi / 4)   # octant edges
+    x = (m * np.cos(ang)).astype(np.float32)
+    y = (m * np.sin(ang)).astype(np.float32)
+    ref = np.arctan2(y.astype(np.float64), x.astype(np.float64))
+    for ulp in (-1, 0, 1):
+        got = _phase_f32(y, x, consts, ulp)
+        assert np.abs(got.astype(np.float64) - ref).max() < 5e-7, ulp
+    z = np.float32(0.0)
+    cases = [(z, np.float32(1.0), 0.0), (-z, np.float32(1.0), -0.0),
+             (z, np.float32(-1.0), np.pi), (-z, np.float32(-1.0), -np.pi),
+             (np.float32(1.0), -z, np.pi / 2), (np.float32(-2.0), z, -np.pi / 2)]
+    for yy, xx, want in cases:
+        got = float(_phase_f32(np.array([yy]), np.array([xx]), consts)[0])
+        assert got == pytest.approx(want, abs=3e-7) and np.signbit(got) == np.signbit(want)
+    tiny = _phase_f32(np.array([1e-31], np.float32), np.array([-1e-31], np.float32), consts)
+    both0 = _phase_f32(np.array([0.0], np.float32), np.array([-0.0], np.float32), consts)
+    huge = _phase_f32(np.array([np.inf], np.float32), np.array([1.0], np.float32), consts)
+    assert np.isnan(tiny).all() and np.isnan(both0).all() and np.isnan(huge).all()
