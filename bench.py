@@ -323,6 +323,14 @@ def main():
                      "launches_timed": f32["launches_timed"]},
         "without_diagnostics": {"value": f32["rate_no_diag"], "steps": K},
     }
+    # the paper's own evolution rate, for context only (another GPU, and its
+    # figure excludes the diagnostics): 7.75e-10 GPU-seconds per site-update
+    # for the three evolution kernels at 512^3 (Sec. 3, performance comparison)
+    line["paper_context"] = {
+        "value": 1.0 / 7.75e-10, "unit": "site-updates/s",
+        "hardware": "NVIDIA Quadro P5000 (the paper's GPU, Sec. 3), FP32",
+        "workload": "512^3, evolution kernels only (no diagnostics)",
+        "ratio_of_value_without_diagnostics": f32["rate_no_diag"] * 7.75e-10}
     tr = line["roofline"]["traffic"]
     if tr is not None:
         # measured HBM bytes per launch (profiler counters) at this run's kernel time
