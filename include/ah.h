@@ -71,8 +71,11 @@ enum {
     AH_KERNEL_TILED = 2,      /* z-streaming tiles with LDS-staged phasors and plaquettes  */
     AH_KERNEL_TILED2 = 3      /* two steps per pass over memory: each block advances its
                                  tile S_n -> S_{n+2}, recomputing S_{n+1} on a one-site
-                                 ring around it; needs AH_LAYOUT_20.  Steps that measure
-                                 and an odd step left over use the AH_KERNEL_TILED pass.   */
+                                 ring around it; needs AH_LAYOUT_20.  A measured state
+                                 takes the AH_KERNEL_TILED pass with the fused measurement,
+                                 or in FP32, when the next stop is an even number of steps
+                                 away, a read-only measuring pass and then pairs; an odd
+                                 step left over takes the AH_KERNEL_TILED pass.            */
 };
 
 enum {
