@@ -40,9 +40,14 @@ inline void tiled2_defaults(bool fp64, int nx, int ny, int nz, int &ty, int &cz)
         ty = tiled2_default_ty(fp64, &ny, &w, 1);
     }
     if (cz <= 0) {
-        // long chunks amortise the two extra planes of step one; aim at ~2048 blocks
+        // long chunks amortise the two extra planes of step one; aim at ~2048
+        // blocks, but with at most 192 planes per chunk (at 1024^3 FP32, 2
+        // chunks of 512 planes take 23.1 ms per pair, 4 of 256 23.8 ms, and
+        // 5-7 chunks of 205-147 planes 21.4-21.5 ms)
         const long tiles_xy = (long)(nx / 64) * ((ny + ty - 1) / ty);
         long chunks = (2048 + tiles_xy - 1) / tiles_xy;
+        if (chunks < (nz + 191) / 192)
+            chunks = (nz + 191) / 192;
         const long max_chunks = (nz + 31) / 32;
         if (chunks > max_chunks)
             chunks = max_chunks;
