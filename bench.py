@@ -55,55 +55,67 @@ def parse():
 
 def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15):
     """Time `steps` steps with the measurement cadence after `warmup` steps,
-    then the same number of steps without diagnostics, then single launches
-    of the dominant kernel.  Returns a dict."""
+    then the same number of steps without diagnostics.  Both timed regions are
+    one library call per pass (one step, or a pair with the two-step kernel),
+    each bracketed by events on the library's stream, so the dominant kernel's
+    duration is read inside the timed region from the calls that measured
+    nothing (each one launch of it after a few-microsecond bookkeeping kernel).
+    Returns a dict."""
     # tau_end = n dx / 2, half a light-crossing time (Sec. 2), with a(tau_end) = 1
     p = AH.Params(n, n, n, precision=prec, dx=0.5, dt=0.1, tau0=0.0, tau_ref=n * 0.5 / 2.0,
                   era_p=2.0, s=0.0, seed=2024,
                   layout=AH.AH_LAYOUT_20 if layout == 20 else AH.AH_LAYOUT_15)
     # the library's choice: pairs through the two-step kernel in the 20-plane layout
     two = layout == 20 and kernel in (AH.AH_KERNEL_TILED2, AH.AH_KERNEL_AUTO)
+    per = 2 if two else 1
     planes = AH.alloc_planes(p)
     ctx = AH.Context([p], [planes])
     if kernel != AH.AH_KERNEL_AUTO:
         ctx.set_kernel(kernel)
-    stream = torch.cuda.current_stream()
+    stream = ctx.stream
     ctx.step(warmup)
     torch.cuda.synchronize()
 
-    def timed(fn):
-        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def timed_passes(measure):
+        calls, obs = [], []
+        t0, t1 = ev(), ev()
         torch.cuda.synchronize()
         t0.record(stream)
-        out = fn()
+        done = 0
+        while done < steps:
+            # pairs from even step counts, so the calls follow the schedule one
+            # call of all the steps would take
+            k = min(per - ctx.current_step() % per, steps - done)
+            a, b = ev(), ev()
+            a.record(stream)
+            o = ctx.step(k, measure_every=MEASURE_EVERY) if measure else ctx.step(k)
+            b.record(stream)
+            calls.append((a, b, k == per and not o))
+            obs += o or []
+            done += k
         t1.record(stream)
         torch.cuda.synchronize()
-        return t0.elapsed_time(t1), out
+        plain = sorted(a.elapsed_time(b) for a, b, one in calls if one)
+        if not plain:
+            raise SystemExit("bench.py: no unmeasured %d-step call to time the kernel by; "
+                             "give more --steps" % per)
+        return t0.elapsed_time(t1), plain, obs
 
     # whole-job throughput with the measurement cadence (the reported value)
-    ms, obs = timed(lambda: ctx.step(steps, measure_every=MEASURE_EVERY))
+    ms, kt, obs = timed_passes(True)
     # and without diagnostics (from a step index of the same parity)
-    ms_nd, _ = timed(lambda: ctx.step(steps))
-
-    # dominant kernel: calls that run one launch of it (one pass: one step, or
-    # a pair with the two-step kernel), bracketed by events on the same stream
-    per = 2 if two else 1
-    k = max(5, min(steps, 20))
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(k)]
-    for a, b in evs:
-        a.record(stream)
-        ctx.step(per)
-        b.record(stream)
-    torch.cuda.synchronize()
-    kt = sorted(a.elapsed_time(b) for a, b in evs)
+    ms_nd, _, _ = timed_passes(False)
     last = obs[-1][0] if obs else None
     ctx.close()
     del planes
     torch.cuda.empty_cache()
     return {"rate": n ** 3 * steps / (ms * 1e-3), "ms_per_step": ms / steps,
-            "rate_no_diag": n ** 3 * steps / (ms_nd * 1e-3), "kernel_ms": kt[len(kt) // 2],
-            "kernel_ms_mean": sum(kt) / len(kt), "launches_timed": k, "per": per, "last": last}
+            "rate_no_diag": n ** 3 * steps / (ms_nd * 1e-3), "kernel_ms": sum(kt) / len(kt),
+            "kernel_ms_median": kt[len(kt) // 2], "launches_timed": len(kt), "per": per,
+            "last": last}
 
 
 def run_slab(AH, torch, passes=30, nxy=1024, nz=128):
@@ -136,30 +148,26 @@ def run_slab(AH, torch, passes=30, nxy=1024, nz=128):
         ctx.step(2)
         refill()
     torch.cuda.synchronize()
+    # one pass and one refill at a time, each bracketed by events, inside the timed region
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    marks = []
     ev[0].record(stream)
     for _ in range(passes):
-        ctx.step(2)
-        refill()
-    ev[1].record(stream)
-    torch.cuda.synchronize()
-    ms = ev[0].elapsed_time(ev[1])
-    kt, ct = [], []
-    for _ in range(10):
         a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         a.record(stream)
         ctx.step(2)
         b.record(stream)
         refill()
         c.record(stream)
-        torch.cuda.synchronize()
-        kt.append(a.elapsed_time(b))
-        ct.append(b.elapsed_time(c))
+        marks.append((a, b, c))
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    kt = [a.elapsed_time(b) for a, b, _ in marks]
+    ct = [b.elapsed_time(c) for _, b, c in marks]
     ctx.close()
     del planes
     torch.cuda.empty_cache()
-    kt.sort()
-    ct.sort()
     sites = nxy * nxy * nz
     plane_bytes = nxy * nxy * 4
     # per pass and face: phi, A on two planes, Pi, E on one (15 plane-values)
@@ -168,9 +176,9 @@ def run_slab(AH, torch, passes=30, nxy=1024, nz=128):
                         f"over {nxy // nz} GPUs), {H} halo planes a side refilled by device "
                         "copies from its own faces before every two-step pass",
             "value": sites * 2 * passes / (ms * 1e-3), "unit": "site-updates/s",
-            "ms_per_pass": ms / passes, "kernel_ms": kt[len(kt) // 2],
-            "halo_refill_ms": ct[len(ct) // 2],
-            "kernel_frac": BYTES_PER_SITE["f32"] * sites * 2 / (kt[len(kt) // 2] * 1e-3) / 1e9
+            "ms_per_pass": ms / passes, "kernel_ms": sum(kt) / len(kt),
+            "halo_refill_ms": sum(ct) / len(ct),
+            "kernel_frac": BYTES_PER_SITE["f32"] * sites * 2 / (sum(kt) / len(kt) * 1e-3) / 1e9
             / HBM_PEAK_GBS,
             "exchange_bytes_per_face_per_pass": face_bytes,
             "exchange_ms_at_153GBs_per_link": face_bytes / 153e9 * 1e3}
@@ -319,7 +327,7 @@ def main():
                      "traffic": profiled_traffic("f32", args.layout, args.kernel, n),
                      "kernel": kname, "steps_per_launch": per32,
                      "bytes_per_site_update": BYTES_PER_SITE["f32"], "kernel_ms": kms32,
-                     "kernel_ms_mean": f32["kernel_ms_mean"],
+                     "kernel_ms_median": f32["kernel_ms_median"],
                      "launches_timed": f32["launches_timed"]},
         "without_diagnostics": {"value": f32["rate_no_diag"], "steps": K},
     }
