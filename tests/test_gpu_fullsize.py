@@ -7,6 +7,9 @@
 - 1024 x 1024 x 128 (one GPU's share of 1024^3 over 8 GPUs, bench.py's slab
   form): the slab with halo planes closed on itself against the periodic
   lattice, bit for bit.
+- 48 x 128^3 + 16 x 64^3 + 4 x 256^3 (bench.py's ensemble): autotuned tiles, one
+  persistent launch per pair, 10-step graphs, diagnostics every 20 steps, against
+  one launch per realization, bit for bit, past the 64^3 realizations' n_end.
 - 256^3 radiation era, s = 1, to tau = 64 (640 steps, diagnostics every 10):
   fields after 10 steps against the oracle (FP64: 1e-12; FP32 from the
   FP32-rounded start: 1e-5 per field group), diagnostics at step 10 against
@@ -148,6 +151,76 @@ def test_slab_1024x1024x128_equals_periodic():
             assert torch.equal(slab.fields()[:, H:H + nz], ref.fields())
     del tp, ts
     torch.cuda.empty_cache()
+
+
+def _full_ensemble():
+    """48 x 128^3 + 16 x 64^3 + 4 x 256^3 FP32 in the 20-plane layout; realization r:
+    radiation s = 1 if r is even, matter s = 0 if odd, seed 1000 + r, each to its own
+    tau_end = N dx / 2 (n_end = 320, 160, 640 steps)."""
+    ps = []
+    for n, count in ((256, 4), (128, 48), (64, 16)):
+        for _ in range(count):
+            r = len(ps)
+            rad = r % 2 == 0
+            tau_end = n * 0.5 / 2.0
+            ps.append(AH.Params(n, n, n, precision=AH.AH_FP32, dx=0.5, dt=0.1, tau0=0.0,
+                                tau_ref=tau_end, era_p=1.0 if rad else 2.0,
+                                s=1.0 if rad else 0.0, seed=1000 + r,
+                                n_end=int(round(tau_end / 0.1)), layout=AH.AH_LAYOUT_20))
+    return ps
+
+
+def test_full_ensemble_in_benchmark_launch_configuration():
+    """The ensemble form as bench.py times it (autotuned tiles, one persistent launch
+    per pair, 10-step graphs, diagnostics every 20 steps) equals one launch per
+    realization bit for bit over 170 steps, past the n_end = 160 of the 64^3
+    realizations (frozen since), with the same winding counts and energies."""
+    print("CASE test=full_ensemble", flush=True)
+    ps = _full_ensemble()
+    nsteps = 170
+
+    def run(tuned):
+        planes = [AH.alloc_planes(p) for p in ps]
+        c = AH.Context(ps, planes)
+        try:
+            if tuned:
+                c.autotune()
+                c.set_launch(True, 10)
+            else:
+                c.set_launch(False, 0)
+            obs = c.step(nsteps, measure_every=20)
+            steps = [c.current_step(r) for r in range(len(ps))]
+            return c, planes, obs, steps
+        except BaseException:
+            c.close()
+            raise
+
+    ref, ref_planes, ref_obs, ref_steps = run(False)
+    try:
+        got, got_planes, got_obs, got_steps = run(True)
+        try:
+            assert ref_steps == got_steps == [min(nsteps, p.n_end) for p in ps]
+            for r in range(len(ps)):
+                assert torch.equal(got.fields(r), ref.fields(r)), r
+            assert len(got_obs) == len(ref_obs) == nsteps // 20 + 1
+            for row, ref_row in zip(got_obs, ref_obs):
+                for r, (a, b) in enumerate(zip(row, ref_row)):
+                    assert a.step == b.step, r
+                    if b.step >= 0:
+                        assert a.n_wind_dir == b.n_wind_dir and a.net_wind_dir == b.net_wind_dir
+                        assert a.energy == pytest.approx(b.energy, rel=1e-12), r
+                        assert a.sum_lag == pytest.approx(b.sum_lag, rel=1e-12), r
+            # the 64^3 realizations measure up to step 140 and not at 160 (their n_end)
+            small = [r for r, p in enumerate(ps) if p.nx == 64]
+            assert [got_obs[j][small[0]].step for j in range(len(got_obs))] == \
+                [0, 20, 40, 60, 80, 100, 120, 140, -1]
+        finally:
+            got.close()
+            del got_planes
+    finally:
+        ref.close()
+        del ref_planes
+        torch.cuda.empty_cache()
 
 
 def test_config_256cubed_radiation_run(O):
