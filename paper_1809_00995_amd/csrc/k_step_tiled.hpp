@@ -602,7 +602,7 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
 
 // One realization: one block per tile, tiles [tile0, tile0 + gridDim.x).
 // The FP32 read-only measuring kernel at 4-row tiles needs 169 VGPRs unhinted (two
-// wavefronts per SIMD); asked for three it fits in 168 without spilling and runs
+// wavefronts per SIMD); asked for three it fits in 168 with one register spilled and runs
 // 17 % faster (2.78 -> 2.30 ms at 512^3).  The fused measuring step would spill
 // under the same request (3.70 -> 4.33 ms), so it keeps the compiler's choice.
 template <typename T, int TY, int MODE>
