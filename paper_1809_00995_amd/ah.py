@@ -248,8 +248,10 @@ class Context:
         out = (_Obs * self.n_real)()
         wmap = None
         if wind:
-            wmap = torch.zeros(sum(3 * p.sites for p in self.params), dtype=torch.int8,
-                               device=self.planes[0].device)
+            # cleared on the library's stream, which ah_measure synchronises
+            with torch.cuda.stream(self.stream):
+                wmap = torch.zeros(sum(3 * p.sites for p in self.params), dtype=torch.int8,
+                                   device=self.planes[0].device)
         rc = self.lib.ah_measure(self._ctx, out,
                                  C.c_void_p(wmap.data_ptr()) if wmap is not None else None)
         _check(self.lib, self._ctx, rc)
@@ -283,8 +285,14 @@ class Context:
     def fields(self, r: int = 0) -> torch.Tensor:
         """The current state S_n of realization r as a (10, nz + 2 z_halo, ny, nx) tensor (a
         copy)."""
-        idx = torch.tensor(self.current_planes(r), device=self.planes[r].device)
-        return self.planes[r].index_select(0, idx)
+        planes = self.current_planes(r)
+        # copied on the library's stream, after its work; the caller's current
+        # stream then waits for the copy
+        with torch.cuda.stream(self.stream):
+            idx = torch.tensor(planes, device=self.planes[r].device)
+            out = self.planes[r].index_select(0, idx)
+        torch.cuda.current_stream(self.planes[r].device).wait_stream(self.stream)
+        return out
 
     def set_kernel(self, kernel: int, tile_y: int = 0, chunk_z: int = 0):
         _check(self.lib, self._ctx, self.lib.ah_set_kernel(self._ctx, kernel, tile_y, chunk_z))

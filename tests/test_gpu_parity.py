@@ -271,6 +271,27 @@ def test_checkpoint_resume_is_bitwise(prec):
         assert torch.equal(c.fields(), full)
 
 
+def test_context_on_its_own_stream():
+    """A context on a stream of its own (default priority) gives the same fields,
+    observations and winding map as one on the current stream; fields() and
+    measure() order their copies after the library's work on that stream."""
+    _print_case(test="own_stream")
+    p = AH.Params(128, 12, 10, precision=AH.AH_FP32, tau0=0.0, tau_ref=4.0, era_p=1.0, s=1.0,
+                  seed=19, layout=AH.AH_LAYOUT_20)
+    side = torch.cuda.Stream()
+    res = []
+    for stream in (None, side):
+        with AH.Context([p], [AH.alloc_planes(p)], stream=stream) as c:
+            obs = c.step(11, measure_every=5)
+            (m,), (w,) = c.measure(wind=True)
+            f = c.fields()
+            res.append((f.clone(), w.clone(), [o[0].n_wind for o in obs], m.n_wind, m.energy))
+    torch.cuda.synchronize()
+    (f0, w0, n0, m0, e0), (f1, w1, n1, m1, e1) = res
+    assert torch.equal(f0, f1) and torch.equal(w0, w1)
+    assert n0 == n1 and m0 == m1 and e1 == pytest.approx(e0, rel=1e-12)
+
+
 def test_batch_equals_solo_and_n_end():
     """Realizations of different sizes and eras in one context advance exactly
     as they do alone; a realization stops at its n_end."""
