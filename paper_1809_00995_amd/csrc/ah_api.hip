@@ -366,7 +366,7 @@ int build_items2(ah_ctx *c) {
     for (int r : order) {
         const ah_params &q = c->p[r];
         int t = ty, z = c->cz2[r];
-        tiled2_defaults(fp64, q.nx, q.ny, q.nz, t, z);
+        tiled2_defaults(fp64, q.nx, q.ny, q.nz, t, z, false);
         const int tiles = (q.nx / 64) * ((q.ny + ty - 1) / ty) * ((q.nz + z - 1) / z);
         for (int k = 0; k < tiles; ++k)
             items.push_back(BatchItem{ r, k, z, 0 });

@@ -34,27 +34,53 @@ inline int tiled2_default_ty(bool fp64, const int *ny, const long *weight, int n
     return pad_big <= pad_small + 0.02 * total ? big : small;
 }
 
-inline void tiled2_defaults(bool fp64, int nx, int ny, int nz, int &ty, int &cz) {
+// Resident blocks of the two-step kernel on the whole chip: one per compute
+// unit (its LDS holds one block), on the 256 compute units of an MI355X.
+constexpr long kTiled2Slots = 256;
+
+// Default tile height and z-chunk of the two-step kernel (values > 0 are kept).
+// Chunks hold at most 192 planes (at 1024^3 FP32, 2 chunks of 512 planes take
+// 23.1 ms per pair, 4 of 256 23.8 ms, 5-7 of 205-147 planes 21.4-21.5 ms) and
+// at least 32 where nz allows.  For one launch over one realization, a block
+// walks its chunk at a pace set by its own compute unit, so the launch lasts
+// about (rounds of kTiled2Slots blocks) x (planes per chunk + 2); the longest
+// chunks within 1 % of the least such cost are taken (measured per pair:
+// FP64 512^3 171 -> 128 planes 6.49 -> 6.32 ms, FP64 384^3 77 -> 64 planes
+// 3.00 -> 2.79 ms, FP64 256^3 32 -> 43 planes 0.91 -> 0.85 ms, FP32 256^3
+// 32 -> 128 planes 0.40 -> 0.37 ms; FP32 512^3, 1024^3 and the 1024 x 1024 x
+// 128 slab keep 103, 171 and 64 planes).  Work lists of the batched launch
+// (one_launch = false) share the chip between realizations and aim at ~2048
+// blocks per realization instead.
+inline void tiled2_defaults(bool fp64, int nx, int ny, int nz, int &ty, int &cz,
+                            bool one_launch = true) {
     if (ty <= 0) {
         const long w = (long)nx * nz;
         ty = tiled2_default_ty(fp64, &ny, &w, 1);
     }
-    if (cz <= 0) {
-        // long chunks amortise the two extra planes of step one; aim at ~2048
-        // blocks, but with at most 192 planes per chunk (at 1024^3 FP32, 2
-        // chunks of 512 planes take 23.1 ms per pair, 4 of 256 23.8 ms, and
-        // 5-7 chunks of 205-147 planes 21.4-21.5 ms)
-        const long tiles_xy = (long)(nx / 64) * ((ny + ty - 1) / ty);
-        long chunks = (2048 + tiles_xy - 1) / tiles_xy;
-        if (chunks < (nz + 191) / 192)
-            chunks = (nz + 191) / 192;
-        const long max_chunks = (nz + 31) / 32;
-        if (chunks > max_chunks)
-            chunks = max_chunks;
-        if (chunks < 1)
-            chunks = 1;
-        cz = (int)((nz + chunks - 1) / chunks);
+    if (cz > 0)
+        return;
+    const long tiles_xy = (long)(nx / 64) * ((ny + ty - 1) / ty);
+    long lo = (nz + 191) / 192, hi = (nz + 31) / 32;
+    if (lo < 1)
+        lo = 1;
+    if (hi < lo)
+        hi = lo;
+    long chunks = lo;
+    if (one_launch) {
+        auto cost = [&](long k) {
+            const long len = (nz + k - 1) / k, used = (nz + len - 1) / len;
+            return (double)((tiles_xy * used + kTiled2Slots - 1) / kTiled2Slots) * (len + 2);
+        };
+        double least = cost(lo);
+        for (long k = lo + 1; k <= hi; ++k)
+            least = cost(k) < least ? cost(k) : least;
+        while (cost(chunks) > 1.01 * least)   // ends at the least-cost count at the latest
+            ++chunks;
+    } else {
+        chunks = (2048 + tiles_xy - 1) / tiles_xy;
+        chunks = chunks < lo ? lo : (chunks > hi ? hi : chunks);
     }
+    cz = (int)((nz + chunks - 1) / chunks);
 }
 
 // Whether every plane of an nx*ny*nz lattice of elem-byte values is below
