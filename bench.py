@@ -267,12 +267,13 @@ def cpu_model():
 
 
 def cpu_baseline():
-    """The FP64 oracle on a bounded sample on this host: 256^3 x 24 steps on all the
-    threads OpenMP gives it, and 128^3 x 6 steps on one thread (a child process with
-    OMP_NUM_THREADS=1, which touches no GPU)."""
+    """The FP64 oracle on a bounded sample of the benchmark's workload on this host: the
+    512^3 lattice for 6 steps (about 13 s) on all the threads OpenMP gives it, and
+    128^3 x 6 steps on one thread (a child process with OMP_NUM_THREADS=1, which
+    touches no GPU)."""
     import subprocess
     import oracle as O
-    n, k = 256, 24
+    n, k = 512, 6
     rate, dt = oracle_rate(n, k)
     out = {"value": rate, "unit": "site-updates/s", "cores": O.threads(), "kind": "oracle",
            "sample": f"FP64 CPU oracle, {n}^3 matter era s=0, {k} steps ({dt:.1f} s)",
