@@ -221,9 +221,9 @@ def run_ensemble(AH, torch, batched, graph_steps, tune, layout=20):
     planes = [AH.alloc_planes(p) for p in ps]
     ctx = AH.Context(ps, planes)
     tuning = None
-    if tune:
-        tuning = ctx.autotune()
     ctx.set_launch(batched, graph_steps)
+    if tune:
+        tuning = ctx.autotune()               # for the launch form just set
     ctx.step(1)                                  # first-launch costs outside the timing
     torch.cuda.synchronize()
     total = sum(p.sites * (p.n_end - 1) for p in ps)

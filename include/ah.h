@@ -257,12 +257,16 @@ int ah_set_launch(ah_ctx *ctx, int32_t batched, int32_t graph_steps);
  * Autotuner: times the tiled step kernel (AH_KERNEL_TILED2 when that is the
  * selected or automatic choice, else AH_KERNEL_TILED) for candidate tile
  * heights and z-chunks on a scratch lattice of each distinct shape of the
- * context (the caller's fields are not touched; scratch of up to 20 planes of
- * nx*ny*min(nz,128) is allocated and freed), installs the tile height with
+ * context (the caller's fields are not touched), installs the tile height with
  * the least estimated total time per step and the best z-chunk for each
  * realization, and returns them in *tile_y and chunk_z[n_real] (either may be
- * NULL).  Needs the tiled kernel (AH_E_STATE otherwise).  Synchronises the
- * stream.
+ * NULL).  It tunes for the launch form in force, so call ah_set_launch first:
+ * with one launch per realization the scratch lattice is the shape itself
+ * (nx*ny*min(nz,128), up to 20 planes); in the batched form it is a lattice of
+ * the same nx, ny, tall enough that every candidate chunk fills the chip (up
+ * to about 2^26 sites, 20 planes; the shape itself if that allocation fails).
+ * The scratch is freed before returning.  Needs the tiled kernel (AH_E_STATE
+ * otherwise).  Synchronises the stream.
  */
 int ah_autotune(ah_ctx *ctx, int32_t *tile_y, int32_t *chunk_z);
 

@@ -910,8 +910,9 @@ int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
     if (c->zh > 0)
         return fail(c, AH_E_STATE, "autotuning is not available for slabs");
     const bool fp64 = c->prec == AH_FP64;
-    // the kernel that runs the unmeasured steps
+    // the kernel that runs the unmeasured steps, and in which launch form
     const bool two = use_tiled2(c);
+    const bool for_batch = batch_ok(c);
     const int ty_cap = c->batched ? tiled_ty_max(fp64, MODE_STEP_MEASURE) : tiled_ty_max(fp64, MODE_STEP);
     std::vector<int> tys;
     for (int t : { 4, 5, 8, 9, 16 })
@@ -957,13 +958,35 @@ int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
         hip_ok(hipMalloc(&d_step, sizeof(int64_t)), "hipMalloc") &&
         hip_ok(hipMalloc(&d_copy, sizeof(int32_t)), "hipMalloc")) {
         for (Shape &sh : shapes) {
-            // time a slab of at most 128 planes: the cost per plane is what is tuned
-            const int nzs = std::min(sh.nz, 128);
-            const int64_t N = (int64_t)sh.nx * sh.ny * nzs;
+            // The cost per plane is what is tuned.  With one launch per
+            // realization the shape itself is timed (at most 128 planes), as
+            // it will run.  The batched form keeps the chip busy with many
+            // realizations at once, so there the same tile shape is timed on
+            // a lattice tall enough that every candidate chunk gives at least
+            // four blocks per compute unit: the planes a chunk walks beyond
+            // its own are then weighed at full occupancy (timed on the shape
+            // alone, a 128^3 realization of an ensemble took 16-plane chunks).
+            const int ty_big = tys.back();
+            const long txy = (long)(sh.nx / 64) * ((sh.ny + ty_big - 1) / ty_big);
+            const int nz_own = std::min(sh.nz, 128);
+            int nzs = for_batch ? (int)std::min<long>(16384, 128 * ((1024 + txy - 1) / txy)) : nz_own;
+            if (nzs < nz_own)
+                nzs = nz_own;
             const int layout = two ? AH_LAYOUT_20 : AH_LAYOUT_15;
-            const size_t bytes = (size_t)N * plane_count(layout) * (fp64 ? 8 : 4);
-            if (!hip_ok(hipMalloc(&scratch, bytes), "hipMalloc(scratch)"))
+            auto scratch_bytes = [&](int planes_z) {
+                return (size_t)sh.nx * sh.ny * planes_z * plane_count(layout) * (fp64 ? 8 : 4);
+            };
+            hipError_t me = hipMalloc(&scratch, scratch_bytes(nzs));
+            if (me != hipSuccess && nzs > nz_own) {
+                // no room for the tall lattice: time the shape itself
+                (void)hipGetLastError();
+                scratch = nullptr;
+                nzs = nz_own;
+                me = hipMalloc(&scratch, scratch_bytes(nzs));
+            }
+            if (!hip_ok(me, "hipMalloc(scratch)"))
                 break;
+            const int64_t N = (int64_t)sh.nx * sh.ny * nzs;
             const ah_params &q0 = c->p[0];
             RealDesc d{};
             d.base = scratch;
@@ -1002,7 +1025,7 @@ int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
                 double best = 1e300;
                 int best_cz = 8;
                 for (int z : { 8, 16, 32, 64, 128 }) {
-                    if (z > nzs || rc != AH_OK)
+                    if (z > nzs || z > sh.nz || rc != AH_OK)
                         continue;
                     for (int k = 0; k < 4 && rc == AH_OK; ++k) {
                         if (k == 1)

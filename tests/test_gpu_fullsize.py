@@ -184,8 +184,8 @@ def test_full_ensemble_in_benchmark_launch_configuration():
         c = AH.Context(ps, planes)
         try:
             if tuned:
-                c.autotune()
                 c.set_launch(True, 10)
+                c.autotune()
             else:
                 c.set_launch(False, 0)
             obs = c.step(nsteps, measure_every=20)
