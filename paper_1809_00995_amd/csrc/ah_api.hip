@@ -317,6 +317,10 @@ int build_items(ah_ctx *c) {
     for (int r : order) {
         const ah_params &q = c->p[r];
         int t = ty, z = c->cz[r];
+        // with pairs through the two-step kernel, the single-step passes of
+        // the batch (measured and odd steps) walk the chunks tuned for it
+        if (z <= 0 && use_tiled2(c))
+            z = c->cz2[r];
         tiled_defaults(fp64, q.nx, q.ny, q.nz, t, z);
         const int tiles = (q.nx / 64) * ((q.ny + ty - 1) / ty) * ((q.nz + z - 1) / z);
         for (int k = 0; k < tiles; ++k)
