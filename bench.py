@@ -13,8 +13,10 @@ reductions) is the headline ``value``, in the 20-plane layout where unmeasured
 steps go in pairs through the two-steps-per-pass kernel (``--layout 15``: one
 step per pass).  The other layout, the FP64 kernels and the plain FP64 kernel
 are reported beside it.  ``roofline`` is for the dominant kernel (the step
-kernel) from HIP events around calls that run exactly one launch of it;
-``cpu_baseline`` times the FP64 CPU oracle on a bounded sample on this host.
+kernel): its mean launch time is taken inside the timed region, from HIP events
+on the library's stream around the passes that measured nothing (one launch of
+it each, after a few-microsecond bookkeeping kernel); ``cpu_baseline`` times the
+FP64 CPU oracle on a bounded sample of the same workload on this host.
 """
 from __future__ import annotations
 
