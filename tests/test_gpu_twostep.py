@@ -166,22 +166,34 @@ def test_two_step_measurements_graphs_and_n_end(prec):
         assert gs[0] == pytest.approx(ref_g[0], rel=1e-12, abs=1e-300)
 
 
-def test_two_step_autotune_keeps_results():
-    _print_case(test="two_step_autotune")
-    p = AH.Params(128, 16, 40, precision=AH.AH_FP32, tau_ref=2.0, era_p=1.0, s=1.0, seed=51,
-                  layout=L20)
-    with AH.Context([p], [AH.alloc_planes(p)]) as c:
+@pytest.mark.parametrize("prec", [AH.AH_FP32, AH.AH_FP64])
+@pytest.mark.parametrize("batched", [False, True], ids=["solo", "batched"])
+def test_two_step_autotune_keeps_results(prec, batched):
+    """The autotuner (for one launch per realization, or for the batched form, where it
+    times a tall scratch lattice) leaves the fields alone and installs tiles that give
+    the same fields bit for bit as untuned single steps."""
+    _print_case(test="two_step_autotune", prec=prec, batched=batched)
+    ps = [AH.Params(128, 16, 40, precision=prec, tau_ref=2.0, era_p=1.0, s=1.0, seed=51,
+                    layout=L20)]
+    if batched:
+        ps.append(AH.Params(64, 24, 20, precision=prec, tau_ref=2.5, era_p=2.0, s=0.0, seed=52,
+                            layout=L20))
+    with AH.Context(ps, [AH.alloc_planes(p) for p in ps]) as c:
+        c.set_launch(batched, 0)
         c.step(3)
-        before = c.fields().clone()
+        before = [c.fields(r).clone() for r in range(len(ps))]
         ty, cz = c.autotune()
-        assert ty in (4, 8) and cz[0] >= 1
-        assert torch.equal(c.fields(), before)
+        assert ty in ((4, 5) if prec == AH.AH_FP64 else (4, 8, 9))
+        assert len(cz) == len(ps) and all(z >= 1 for z in cz)
+        for r in range(len(ps)):
+            assert torch.equal(c.fields(r), before[r])
         c.step(8)
-        tuned = c.fields().clone()
-    q = AH.Params(**{**p.__dict__, "layout": L15})
-    with AH.Context([q], [AH.alloc_planes(q)]) as c:
+        tuned = [c.fields(r).clone() for r in range(len(ps))]
+    qs = [AH.Params(**{**p.__dict__, "layout": L15}) for p in ps]
+    with AH.Context(qs, [AH.alloc_planes(q) for q in qs]) as c:
         c.step(11)
-        assert torch.equal(c.fields(), tuned)
+        for r in range(len(ps)):
+            assert torch.equal(c.fields(r), tuned[r]), r
 
 
 @pytest.mark.parametrize("prec", [AH.AH_FP32, AH.AH_FP64])
