@@ -230,7 +230,8 @@ int ah_current_step(const ah_ctx *ctx, int32_t r, int64_t *n);
  * tile: tile_y rows of 64 sites per block and chunk_z planes per block along
  * z (>= 1); 0 picks the library default.  tile_y: AH_KERNEL_TILED 2, 4, 8, or
  * 16 for FP32; AH_KERNEL_TILED2 4, 8 or 9 for FP32, 4 or 5 for FP64 (its
- * measuring and odd steps keep the AH_KERNEL_TILED defaults).  The tiled kernels need
+ * measuring and odd steps keep the AH_KERNEL_TILED defaults, except that in the
+ * batched form they walk the two-step kernel's z-chunks).  The tiled kernels need
  * nx % 64 == 0 in every realization, AH_KERNEL_TILED2 also AH_LAYOUT_20
  * (AH_E_INVALID otherwise).  Results do not depend on the choice beyond
  * floating-point rounding of the same formulas; the tiled variants of one
