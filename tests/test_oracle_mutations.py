@@ -38,6 +38,19 @@ MUT = [
  ("pressure grad 1/3", "double pres = a2 * K - a2 * G / 3.0 + g * (EE + BB) / 3.0 - h * V;", "double pres = a2 * K - a2 * G + g * (EE + BB) / 3.0 - h * V;"),
  ("pressure pot sign", "double pres = a2 * K - a2 * G / 3.0 + g * (EE + BB) / 3.0 - h * V;", "double pres = a2 * K - a2 * G / 3.0 + g * (EE + BB) / 3.0 + h * V;"),
  ("init phase offset", "double theta = OR_TWO_PI * u - OR_PI;", "double theta = OR_PI * u - OR_PI;"),
+ # the Lagrangian density, the weights of <v^2>_X and xi_L (Eqs. (9)-(10), (12))
+ ("L weight of num is rho", "acc[S_NUM_L] += K * lag;", "acc[S_NUM_L] += K * rho;"),
+ ("V weight of den is L", "acc[S_DEN_V] += G * V;", "acc[S_DEN_V] += G * lag;"),
+ ("L gradient sign", "double lag = a2 * K - a2 * G + g * (EE - BB) - h * V;", "double lag = a2 * K + a2 * G + g * (EE - BB) - h * V;"),
+ ("L magnetic sign", "double lag = a2 * K - a2 * G + g * (EE - BB) - h * V;", "double lag = a2 * K - a2 * G + g * (EE + BB) - h * V;"),
+ ("L electric sign", "double lag = a2 * K - a2 * G + g * (EE - BB) - h * V;", "double lag = a2 * K - a2 * G + g * (-EE - BB) - h * V;"),
+ ("L potential sign", "double lag = a2 * K - a2 * G + g * (EE - BB) - h * V;", "double lag = a2 * K - a2 * G + g * (EE - BB) + h * V;"),
+ ("v2 is R/(1+R)", "obs->v2[k] = 2.0 * R / (1.0 + R);", "obs->v2[k] = R / (1.0 + R);"),
+ ("mu is pi sigma^2", "? a * sqrt(-(OR_TWO_PI * s2) * vbox / obs->sum_lag)", "? a * sqrt(-(OR_PI * s2) * vbox / obs->sum_lag)"),
+ ("mu is 2 pi sigma", "? a * sqrt(-(OR_TWO_PI * s2) * vbox / obs->sum_lag)", "? a * sqrt(-(OR_TWO_PI * p->sigma) * vbox / obs->sum_lag)"),
+ ("xi_L without a", "? a * sqrt(-(OR_TWO_PI * s2) * vbox / obs->sum_lag)", "? sqrt(-(OR_TWO_PI * s2) * vbox / obs->sum_lag)"),
+ ("eos without 3", "obs->v2_eos = 0.5 * (1.0 + 3.0 * obs->pres_lag / obs->rho_lag);", "obs->v2_eos = 0.5 * (1.0 + obs->pres_lag / obs->rho_lag);"),
+ ("eos density weight", "acc[S_RHO_L] += rho * lag;", "acc[S_RHO_L] += rho * rho;"),
 ]
 
 
@@ -52,8 +65,14 @@ def test_pins_catch_planted_mistake(tmp_path, name, orig, planted):
     src = path.read_text()
     assert src.count(orig) == 1, f"{name}: the oracle text to mutate is not unique or gone"
     path.write_text(src.replace(orig, planted))
+    # copies run side by side under a parallel test runner share the cores
+    # (OpenMP threads that spin on a shared core slow the pins a hundredfold)
+    env = dict(os.environ)
+    workers = int(os.environ.get("PYTEST_XDIST_WORKER_COUNT", "1"))
+    if workers > 1:
+        env["OMP_NUM_THREADS"] = str(max(1, (os.cpu_count() or 1) // workers))
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        "tests/test_oracle_pins.py"], cwd=tmp_path, capture_output=True,
-                       text=True, timeout=600)
+                        "tests/test_oracle_pins.py", "tests/test_oracle_pins_strings.py"],
+                       cwd=tmp_path, capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode != 0, f"{name}: no pin failed\n{r.stdout[-2000:]}"
     assert "failed" in r.stdout or "error" in r.stdout.lower(), r.stdout[-2000:]
