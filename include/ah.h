@@ -207,6 +207,41 @@ int ah_step(ah_ctx *ctx, int64_t nsteps, int32_t measure_every, ah_obs *out,
  */
 int ah_measure(ah_ctx *ctx, ah_obs *out, int8_t *wind_dev);
 
+/* Most states one ah_measure_noalloc call measures: the capacity of the
+ * library's static device scratch (a descriptor, the coefficients and one
+ * slot of sums per state: 36 KB per GPU). */
+#define AH_NOALLOC_MAX_REAL 64
+
+/*
+ * ah_measure without a context and without allocating anything, for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Measures, with the kernels
+ * ah_measure uses and the diagnostics it returns (Sec. 2, Eqs. (9)-(12)), the
+ * state S_n with n = p[r].step0 held in planes 0-9 of buf[r] (the first copy;
+ * ah_current_planes says whether a context's current state is there), for
+ * 1 <= n_real <= AH_NOALLOC_MAX_REAL realizations described as for ah_init
+ * and validated the same way (init, seed and n_end are not used).
+ *  - out_dev: device array of n_real ah_obs, written on the stream;
+ *    wind_dev: NULL or a device array as for ah_measure.
+ *  - Every operation is issued on hip_stream (a hipStream_t or NULL) and the
+ *    call returns without waiting: out_dev holds the results once the stream
+ *    has passed this point.  Non-finite sites are counted in
+ *    out_dev[r].nonfinite (the call cannot see them, so it does not return
+ *    AH_E_NONFINITE).
+ *  - Scratch: the library's static device array (one per GPU, held until the
+ *    process ends).  Its address is looked up, with the device current, by
+ *    the first ah_init or ah_measure_noalloc call on that device: make one such
+ *    call before capturing a graph.  Each call clears the part it uses, and
+ *    the array keeps the last call's contents, so calls that overlap on one GPU
+ *    (other streams, other host threads) race and must be ordered by the
+ *    caller.
+ *  - Errors (AH_E_INVALID for n_real outside [1, AH_NOALLOC_MAX_REAL] or a
+ *    bad realization, AH_E_DOMAIN, AH_E_HIP) are returned before any device
+ *    work except a failed launch; ah_last_error(NULL) gives the message.
+ */
+int ah_measure_noalloc(int32_t n_real, const ah_params *p, const ah_buffers *buf,
+                       ah_obs *out_dev, int8_t *wind_dev, void *hip_stream);
+
 /*
  * Gauss-law residual of the current state (discrete Noether charge of the
  * lattice action under time-independent gauge transformations, conserved by

@@ -24,9 +24,11 @@ AH_KERNEL_AUTO, AH_KERNEL_PLAIN, AH_KERNEL_TILED, AH_KERNEL_TILED2 = 0, 1, 2, 3
 AH_LAYOUT_15, AH_LAYOUT_20 = 0, 1
 
 FIELDS = ("phi_re", "phi_im", "pi_re", "pi_im", "ax", "ay", "az", "ex", "ey", "ez")
+AH_NOALLOC_MAX_REAL = 64
+
 EXPORTED = ("ah_error_string", "ah_last_error", "ah_init", "ah_step", "ah_measure",
-            "ah_gauss_residual", "ah_current_planes", "ah_current_step", "ah_set_kernel",
-            "ah_set_launch", "ah_autotune", "ah_free")
+            "ah_measure_noalloc", "ah_gauss_residual", "ah_current_planes", "ah_current_step",
+            "ah_set_kernel", "ah_set_launch", "ah_autotune", "ah_free")
 
 
 class AHError(RuntimeError):
@@ -85,6 +87,8 @@ def load_library(path: str = LIB_PATH):
     lib.ah_init.argtypes = [P(C.c_void_p), C.c_int32, P(_Params), P(_Buffers), C.c_void_p]
     lib.ah_step.argtypes = [C.c_void_p, C.c_int64, C.c_int32, P(_Obs), C.c_int64, P(C.c_int64)]
     lib.ah_measure.argtypes = [C.c_void_p, P(_Obs), C.c_void_p]
+    lib.ah_measure_noalloc.argtypes = [C.c_int32, P(_Params), P(_Buffers), C.c_void_p,
+                                       C.c_void_p, C.c_void_p]
     lib.ah_gauss_residual.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
     lib.ah_current_planes.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32)]
     lib.ah_current_step.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64)]
@@ -190,6 +194,40 @@ def alloc_planes(p: Params, device="cuda") -> torch.Tensor:
     """Caller-owned field storage: 15 or 20 planes by layout (see include/ah.h), shape
     (planes, nz + 2 z_halo, ny, nx)."""
     return torch.empty((p.planes, p.nz_stored, p.ny, p.nx), dtype=p.dtype, device=device)
+
+
+OBS_BYTES = C.sizeof(_Obs)
+
+
+def measure_noalloc(params: Sequence[Params], planes: Sequence[torch.Tensor], out: torch.Tensor,
+                    wind: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None):
+    """ah_measure_noalloc: the diagnostics of S_{step0} held in planes 0-9 of each tensor,
+    without a context and without any allocation in the library.  ``out`` is a caller-owned
+    uint8 device tensor of at least ``len(params) * OBS_BYTES`` bytes that receives the
+    ah_obs records; ``wind`` None or an int8 device tensor as for ``Context.measure``.
+    Asynchronous on ``stream`` (default: the current stream); decode ``out`` with
+    ``obs_from_bytes`` once the stream has reached this call."""
+    lib = load_library()
+    n = len(params)
+    if n != len(planes) or out.dtype != torch.uint8 or not out.is_cuda or \
+            out.numel() < n * OBS_BYTES or not out.is_contiguous():
+        raise ValueError("one planes tensor per realization and a contiguous uint8 device "
+                         "tensor of n_real * OBS_BYTES bytes are required")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    cp = (_Params * n)(*[p._c() for p in params])
+    cb = (_Buffers * n)(*[_Buffers(t.data_ptr()) for t in planes])
+    rc = lib.ah_measure_noalloc(n, cp, cb, C.c_void_p(out.data_ptr()),
+                                C.c_void_p(wind.data_ptr()) if wind is not None else None,
+                                C.c_void_p(st.cuda_stream))
+    _check(lib, None, rc)
+    return out
+
+
+def obs_from_bytes(raw, n: int) -> list:
+    """Decode n ah_obs records from host bytes (or a CPU uint8 tensor)."""
+    if isinstance(raw, torch.Tensor):
+        raw = raw.cpu().numpy().tobytes()
+    return [Obs._from(_Obs.from_buffer_copy(raw, k * OBS_BYTES)) for k in range(n)]
 
 
 def _check(lib, ctx, rc):

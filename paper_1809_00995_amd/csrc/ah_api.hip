@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -102,6 +103,33 @@ int grid_for(int64_t n, int threads, int cap) {
 
 // Stored sites per plane: nx*ny*nz, plus the halo planes of a slab.
 int64_t sites_of(const ah_params &q) { return (int64_t)q.nx * q.ny * (q.nz + 2 * q.z_halo); }
+
+// Device description of realization q stored at `planes`.
+RealDesc make_desc(const ah_params &q, void *planes) {
+    RealDesc d;
+    d.base = (char *)planes;
+    d.nx = q.nx;
+    d.ny = q.ny;
+    d.nz = q.nz;
+    d.elem = q.precision == AH_FP64 ? 8 : 4;
+    d.layout = q.layout;
+    d.zh = q.z_halo;
+    d.N = sites_of(q);
+    d.dx = q.dx;
+    d.dt = q.dt;
+    d.tau0 = q.tau0;
+    d.tau_ref = q.tau_ref;
+    d.era_p = q.era_p;
+    d.s = q.s;
+    d.lambda0 = q.lambda0;
+    d.e0 = q.e0;
+    d.sigma = q.sigma;
+    d.step0 = q.step0;
+    d.n_end = q.n_end;
+    d.s_late = q.s_late;
+    d.tau_s = q.tau_s;
+    return d;
+}
 
 double scale_factor_host(const ah_params &p, double tau) {
     double t = tau > 0.0 ? tau : 0.0;
@@ -542,6 +570,65 @@ void release(ah_ctx *c) {
     delete c;
 }
 
+// ---- measurement without a context: the static scratch ----------------
+//
+// ah_measure_noalloc keeps its descriptors, coefficients and sums in one
+// file-scope device array instead of memory it allocates.  Each GPU the
+// library runs on holds its own copy of the array (until the process ends);
+// host code reaches it only through the address hipGetSymbolAddress returns
+// for the device that is current, never through the array's name.
+
+constexpr size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+constexpr size_t kNoallocDescOff = 0;
+constexpr size_t kNoallocCoefOff = align256(AH_NOALLOC_MAX_REAL * sizeof(RealDesc));
+constexpr size_t kNoallocSlotOff = kNoallocCoefOff + align256(AH_NOALLOC_MAX_REAL * sizeof(Coef));
+constexpr size_t kNoallocBytes = kNoallocSlotOff + align256(AH_NOALLOC_MAX_REAL * sizeof(Slot));
+static_assert(sizeof(Slot) % 8 == 0, "slots are cleared in 64-bit words");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+} // namespace
+
+static __device__ __align__(256) unsigned long long scratch[kNoallocBytes / 8];
+
+namespace {
+
+// Device address of `scratch` on the current device, looked up once per device.
+int noalloc_scratch(char **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(nullptr, AH_E_HIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(nullptr, AH_E_INVALID, "device %d beyond the %d the library tracks", dev,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(nullptr, AH_E_HIP, "hipGetSymbolAddress(scratch) failed: %s",
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = (char *)g_scratch_ptr[dev];
+    return AH_OK;
+}
+
+// Slot r of the static scratch: its descriptor, the coefficients of S_{step0}
+// (first copy) and zeroed sums.
+__global__ void k_noalloc_setup(RealDesc d, int r, RealDesc *descs, Coef *coefs, Slot *slots) {
+    unsigned long long *w = reinterpret_cast<unsigned long long *>(slots + r);
+    for (int i = threadIdx.x; i < (int)(sizeof(Slot) / 8); i += blockDim.x)
+        w[i] = 0ull;
+    if (threadIdx.x == 0) {
+        descs[r] = d;
+        coefs[r] = coef_at(d, d.step0, 0);
+    }
+}
+
 } // namespace
 
 extern "C" {
@@ -593,30 +680,8 @@ int ah_init(ah_ctx **out, int32_t n_real, const ah_params *p, const ah_buffers *
 
     std::vector<RealDesc> desc(n_real);
     for (int r = 0; r < n_real; ++r) {
-        const ah_params &q = p[r];
-        RealDesc &d = desc[r];
-        d.base = (char *)buf[r].planes;
-        d.nx = q.nx;
-        d.ny = q.ny;
-        d.nz = q.nz;
-        d.elem = c->prec == AH_FP64 ? 8 : 4;
-        d.layout = q.layout;
-        d.zh = q.z_halo;
-        d.N = sites_of(q);
-        d.dx = q.dx;
-        d.dt = q.dt;
-        d.tau0 = q.tau0;
-        d.tau_ref = q.tau_ref;
-        d.era_p = q.era_p;
-        d.s = q.s;
-        d.lambda0 = q.lambda0;
-        d.e0 = q.e0;
-        d.sigma = q.sigma;
-        d.step0 = q.step0;
-        d.n_end = q.n_end;
-        d.s_late = q.s_late;
-        d.tau_s = q.tau_s;
-        c->step[r] = q.step0;
+        desc[r] = make_desc(p[r], buf[r].planes);
+        c->step[r] = p[r].step0;
     }
 
     auto hip_fail = [&](hipError_t e, const char *what) {
@@ -625,6 +690,15 @@ int ah_init(ah_ctx **out, int32_t n_real, const ah_params *p, const ah_buffers *
         return AH_E_HIP;
     };
     hipError_t e;
+    {
+        // set-up of ah_measure_noalloc's static scratch on this device
+        char *unused = nullptr;
+        const int rc = noalloc_scratch(&unused);
+        if (rc != AH_OK) {
+            release(c);
+            return rc;
+        }
+    }
     if ((e = hipMalloc(&c->d_desc, n_real * sizeof(RealDesc))) != hipSuccess)
         return hip_fail(e, "hipMalloc(desc)");
     if ((e = hipMalloc(&c->d_step, n_real * sizeof(int64_t))) != hipSuccess)
@@ -807,6 +881,63 @@ int ah_measure(ah_ctx *c, ah_obs *out, int8_t *wind_dev) {
         if (out[r].nonfinite > 0)
             return fail(c, AH_E_NONFINITE, "realization %d: %lld non-finite sites", r,
                         (long long)out[r].nonfinite);
+    return AH_OK;
+}
+
+int ah_measure_noalloc(int32_t n_real, const ah_params *p, const ah_buffers *buf,
+                       ah_obs *out_dev, int8_t *wind_dev, void *hip_stream) {
+    g_init_err.clear();
+    if (n_real < 1 || n_real > AH_NOALLOC_MAX_REAL)
+        return fail(nullptr, AH_E_INVALID,
+                    "n_real %d outside [1, %d]: the static scratch holds %d states per call",
+                    (int)n_real, AH_NOALLOC_MAX_REAL, AH_NOALLOC_MAX_REAL);
+    if (!p || !buf || !out_dev)
+        return fail(nullptr, AH_E_INVALID, "need non-NULL params, buffers and out_dev");
+    for (int r = 0; r < n_real; ++r)
+        TRY(validate(p[r], r, buf[r], p[0].precision, p[0].layout));
+    char *base = nullptr;
+    TRY(noalloc_scratch(&base));
+    RealDesc *descs = (RealDesc *)(base + kNoallocDescOff);
+    Coef *coefs = (Coef *)(base + kNoallocCoefOff);
+    Slot *slots = (Slot *)(base + kNoallocSlotOff);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const bool fp64 = p[0].precision == AH_FP64;
+    hipError_t e;
+    for (int r = 0; r < n_real; ++r) {
+        hipLaunchKernelGGL(k_noalloc_setup, dim3(1), dim3(64), 0, st, make_desc(p[r], buf[r].planes),
+                           r, descs, coefs, slots);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return fail(nullptr, AH_E_HIP, "k_noalloc_setup launch failed: %s", hipGetErrorString(e));
+    }
+    // the kernels ah_measure takes by default: tiled where nx % 64 == 0
+    int64_t off = 0;
+    for (int r = 0; r < n_real; ++r) {
+        const ah_params &q = p[r];
+        int8_t *w = wind_dev ? wind_dev + off : nullptr;
+        if (q.nx % 64 == 0) {
+            int rc = launch_step_tiled(fp64, MODE_MEASURE, descs, coefs, r, q.nx, q.ny, q.nz, 0, 0,
+                                       slots + r, w, st);
+            if (rc)
+                return fail(nullptr, AH_E_HIP, "tiled measuring kernel launch failed: %s",
+                            hipGetErrorString((hipError_t)rc));
+        } else {
+            dim3 grid(grid_for(sites_of(q), kMeasureThreads, 4096));
+            if (fp64)
+                hipLaunchKernelGGL(k_measure_plain<double>, grid, dim3(kMeasureThreads), 0, st, descs,
+                                   coefs, r, slots + r, w);
+            else
+                hipLaunchKernelGGL(k_measure_plain<float>, grid, dim3(kMeasureThreads), 0, st, descs,
+                                   coefs, r, slots + r, w);
+            if ((e = hipGetLastError()) != hipSuccess)
+                return fail(nullptr, AH_E_HIP, "measuring kernel launch failed: %s",
+                            hipGetErrorString(e));
+        }
+        off += 3 * sites_of(q);
+    }
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((n_real + 63) / 64)), dim3(64), 0, st, descs,
+                       slots, out_dev, (int)n_real, (int)n_real);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return fail(nullptr, AH_E_HIP, "k_finalize launch failed: %s", hipGetErrorString(e));
     return AH_OK;
 }
 

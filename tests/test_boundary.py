@@ -22,7 +22,7 @@ def declared_functions():
 def test_library_exports_every_declared_entry_point():
     lib = AH.load_library()
     names = declared_functions()
-    assert len(names) == 12
+    assert len(names) == 13
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(B.EXPORTED) == names
@@ -98,6 +98,26 @@ def test_bad_extents_alignment_and_null():
     assert lib.ah_step(None, 1, 0, None, 0, None) == B.AH_E_INVALID
     assert lib.ah_free(None) == B.AH_OK
     assert lib.ah_error_string(B.AH_E_NONFINITE) == b"non-finite field values"
+
+
+def test_noalloc_measure_rejects_bad_sizes_before_device_work():
+    """ah_measure_noalloc holds at most AH_NOALLOC_MAX_REAL states in its static
+    scratch: other counts and NULL arguments fail before any GPU call."""
+    hdr = open(os.path.join(ROOT, "include", "ah.h")).read()
+    assert int(re.search(r"#define AH_NOALLOC_MAX_REAL (\d+)", hdr).group(1)) == \
+        B.AH_NOALLOC_MAX_REAL
+    lib = AH.load_library()
+    n = B.AH_NOALLOC_MAX_REAL + 1
+    ps = (B._Params * n)(*[AH.Params(64, 8, 8)._c() for _ in range(n)])
+    bs = (B._Buffers * n)(*[B._Buffers(4096) for _ in range(n)])
+    assert lib.ah_measure_noalloc(n, ps, bs, 4096, None, None) == B.AH_E_INVALID
+    msg = lib.ah_last_error(None).decode()
+    assert "static scratch" in msg and str(B.AH_NOALLOC_MAX_REAL) in msg
+    assert lib.ah_measure_noalloc(0, ps, bs, 4096, None, None) == B.AH_E_INVALID
+    assert lib.ah_measure_noalloc(1, ps, bs, None, None, None) == B.AH_E_INVALID
+    assert lib.ah_measure_noalloc(1, None, bs, 4096, None, None) == B.AH_E_INVALID
+    bad = (B._Params * 1)(AH.Params(64, 8, 8, dt=0.3)._c())
+    assert lib.ah_measure_noalloc(1, bad, bs, 4096, None, None) == B.AH_E_DOMAIN
 
 
 def test_slab_parameters_are_validated():
