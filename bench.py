@@ -55,7 +55,7 @@ def parse():
     return ap.parse_args()
 
 
-def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15):
+def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15, s=0.0):
     """Time `steps` steps with the measurement cadence after `warmup` steps,
     then the same number of steps without diagnostics.  Both timed regions are
     one library call per pass (one step, or a pair with the two-step kernel),
@@ -65,7 +65,7 @@ def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15):
     Returns a dict."""
     # tau_end = n dx / 2, half a light-crossing time (Sec. 2), with a(tau_end) = 1
     p = AH.Params(n, n, n, precision=prec, dx=0.5, dt=0.1, tau0=0.0, tau_ref=n * 0.5 / 2.0,
-                  era_p=2.0, s=0.0, seed=2024,
+                  era_p=2.0, s=s, seed=2024,
                   layout=AH.AH_LAYOUT_20 if layout == 20 else AH.AH_LAYOUT_15)
     # the library's choice: pairs through the two-step kernel in the 20-plane layout
     two = layout == 20 and kernel in (AH.AH_KERNEL_TILED2, AH.AH_KERNEL_AUTO)
@@ -189,15 +189,42 @@ def run_slab(AH, torch, passes=30, nxy=1024, nz=128):
 # HBM bytes per launch of the dominant kernel from the profiler's byte counters
 # (FETCH_SIZE x 2 + WRITE_SIZE x 1, factors from a 1 GiB device copy measured
 # in the same runs), for the kernel as it was profiled; the summaries and
-# commands are in profiles/.  Keyed by (dtype, layout, kernel option, lattice).
+# commands are in profiles/.  Keyed by (dtype, layout, kernel option, lattice);
+# each figure carries a digest of the kernel's sources and build options when
+# the counters were taken, and is reported only while they are unchanged.
 PROFILED_TRAFFIC_BYTES = {
     # k_step_tiled2<float, 9, true>, profiles/step_tiled2_512cubed.md
-    ("f32", 20, "auto", 512): 11.98e9,
+    ("f32", 20, "auto", 512): (11.98e9, None),
 }
+# sources of the FP32 two-step kernel's translation unit (and its build options)
+KERNEL_SOURCES = ("paper_1809_00995_amd/csrc/k_step_tiled2_f32.hip",
+                  "paper_1809_00995_amd/csrc/k_step_tiled2.hpp",
+                  "paper_1809_00995_amd/csrc/k_step_tiled2_api.hpp",
+                  "paper_1809_00995_amd/csrc/k_step_tiled.hpp",
+                  "paper_1809_00995_amd/csrc/ah_device.hpp",
+                  "include/ah.h",
+                  "paper_1809_00995_amd/build.py")
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def profiled_traffic(dt, layout, kernel, n):
-    return PROFILED_TRAFFIC_BYTES.get((dt, layout, kernel, n))
+    """(bytes per launch, note): None when no counters were taken for this form or
+    the kernel's sources changed since."""
+    v = PROFILED_TRAFFIC_BYTES.get((dt, layout, kernel, n))
+    if v is None:
+        return None, "no counter run for this form"
+    nbytes, digest = v
+    if digest != kernel_digest():
+        return None, "kernel sources changed since the counters were taken"
+    return nbytes, "profiles/step_tiled2_512cubed.md"
 
 
 def ensemble_params(AH, layout=20):
@@ -314,6 +341,10 @@ def main():
           file=sys.stderr, flush=True)
     achieved = BYTES_PER_SITE["f32"] * n ** 3 * per32 / (kms32 * 1e-3) / 1e9
     kname = "two-steps-per-pass kernel" if per32 == 2 else "step kernel"
+    traffic, traffic_note = profiled_traffic("f32", args.layout, args.kernel, n)
+    # the floor of the kernel's own design: one read and one write of the state
+    # per launch, whatever the number of steps it advances
+    floor_bps = BYTES_PER_SITE["f32"] // per32
     line = {
         "metric": "lattice site-updates/s and % HBM roofline, FP32 vs FP64 kernel, 512^3",
         "value": rate32, "unit": "site-updates/s", "n_gpus": 1, "steps": K, "warmup": W,
@@ -327,11 +358,21 @@ def main():
                    "precision": "FP32 fields and stencil, FP64 bookkeeping and reductions"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic("f32", args.layout, args.kernel, n),
+                     "traffic": traffic, "traffic_source": traffic_note,
                      "kernel": kname, "steps_per_launch": per32,
-                     "bytes_per_site_update": BYTES_PER_SITE["f32"], "kernel_ms": kms32,
+                     "bytes_per_site_update": BYTES_PER_SITE["f32"],
+                     "algorithmic_bytes_per_launch": BYTES_PER_SITE["f32"] * n ** 3 * per32,
+                     "kernel_ms": kms32,
                      "kernel_ms_median": f32["kernel_ms_median"],
-                     "launches_timed": f32["launches_timed"]},
+                     "launches_timed": f32["launches_timed"],
+                     "design_floor": {
+                         "bytes_per_site_update": floor_bps,
+                         "note": "one read and one write of the 40 B/site FP32 state per launch "
+                                 "of %d step(s); frac above 1 on the per-step roofline means "
+                                 "fewer bytes than one pass per step" % per32,
+                         "achieved": floor_bps * n ** 3 * per32 / (kms32 * 1e-3) / 1e9,
+                         "frac": floor_bps * n ** 3 * per32 / (kms32 * 1e-3) / 1e9
+                         / HBM_PEAK_GBS}},
         "without_diagnostics": {"value": f32["rate_no_diag"], "steps": K},
     }
     # the paper's own evolution rate, for context only (another GPU, and its
@@ -342,10 +383,10 @@ def main():
         "hardware": "NVIDIA Quadro P5000 (the paper's GPU, Sec. 3), FP32",
         "workload": "512^3, evolution kernels only (no diagnostics)",
         "ratio_of_value_without_diagnostics": f32["rate_no_diag"] * 7.75e-10}
-    tr = line["roofline"]["traffic"]
-    if tr is not None:
+    if traffic is not None:
         # measured HBM bytes per launch (profiler counters) at this run's kernel time
-        line["roofline"]["traffic_GBs"] = tr / (kms32 * 1e-3) / 1e9
+        line["roofline"]["traffic_GBs"] = traffic / (kms32 * 1e-3) / 1e9
+        line["roofline"]["traffic_frac"] = line["roofline"]["traffic_GBs"] / HBM_PEAK_GBS
     if last32 is not None:
         line["last_obs"] = {"step": last32.step, "n_wind": last32.n_wind,
                             "xi_w": last32.xi_w, "v2_L": last32.v2[0]}
@@ -361,6 +402,15 @@ def main():
                           "value_without_diagnostics": f["rate_no_diag"],
                           "kernel_ms": f["kernel_ms"], "steps_per_launch": f["per"],
                           "layout": lay, "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}
+        # the second leg of the 512^3 matter-era workload: s = 1 (true equations of motion)
+        f = run_form(AH, torch, n, AH.AH_FP32, kern, K, W, args.layout, s=1.0)
+        print(f"# fp32 s=1: {f['rate']:.4g} site-updates/s", file=sys.stderr, flush=True)
+        ach = BYTES_PER_SITE["f32"] * n ** 3 * f["per"] / (f["kernel_ms"] * 1e-3) / 1e9
+        line["fp32_s1"] = {"value": f["rate"], "ms_per_step": f["ms_per_step"],
+                           "value_without_diagnostics": f["rate_no_diag"],
+                           "kernel_ms": f["kernel_ms"], "steps_per_launch": f["per"],
+                           "layout": args.layout, "achieved_GBs": ach,
+                           "frac": ach / HBM_PEAK_GBS, "s": 1.0}
         kp = max(10, K // 4)
         fp = run_form(AH, torch, n, AH.AH_FP64, AH.AH_KERNEL_PLAIN, kp, 2)
         print(f"# fp64 plain: {fp['rate']:.4g} site-updates/s", file=sys.stderr, flush=True)
@@ -405,7 +455,8 @@ def main():
     del src, dst
     torch.cuda.empty_cache()
     line["roofline"]["copy_GBs"] = copy_gbs
-    line["roofline"]["frac_of_copy"] = achieved / copy_gbs
+    if traffic is not None:
+        line["roofline"]["traffic_frac_of_copy"] = line["roofline"]["traffic_GBs"] / copy_gbs
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -92,7 +92,7 @@ def test_bad_extents_alignment_and_null():
     mixed = (B._Params * 2)(AH.Params(64, 8, 8)._c(), AH.Params(64, 8, 8, precision=1)._c())
     bufs = (B._Buffers * 2)(B._Buffers(4096), B._Buffers(8192))
     assert lib.ah_init(C.byref(ctx), 2, mixed, bufs, None) == B.AH_E_INVALID
-    mixed = (B._Params * 2)(AH.Params(64, 8, 8)._c(), AH.Params(64, 8, 8, layout=1)._c())
+    mixed = (B._Params * 2)(AH.Params(64, 8, 8, layout=0)._c(), AH.Params(64, 8, 8, layout=1)._c())
     assert lib.ah_init(C.byref(ctx), 2, mixed, bufs, None) == B.AH_E_INVALID
     assert "one layout" in lib.ah_last_error(None).decode()
     assert lib.ah_step(None, 1, 0, None, 0, None) == B.AH_E_INVALID

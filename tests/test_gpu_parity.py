@@ -7,7 +7,12 @@ with different libm implementations, so they differ by rounding only.  FP32
 kernels: 1e-5 on fields after 10 steps, 1e-3 on string length and <v^2> at
 the end, windings compared plaquette by plaquette with mismatches allowed only
 on plaquettes with a link whose phase argument lies within 1e-6 of pi.
+
+These tests hold the 15-plane layout (one step per pass, Pi and E updated in
+place) unless they say otherwise; the 20-plane layout, the library's default
+through the binding, is covered by the two-step, full-size and ensemble tests.
 """
+import functools
 import math
 
 import numpy as np
@@ -22,6 +27,7 @@ AH = pytest.importorskip("paper_1809_00995_amd")
 from tests.gpu_util import (ambiguous_links, fields_np, group_errors, oracle_params,  # noqa: E402
                             plaquette_touches, upload)
 
+P15 = functools.partial(AH.Params, layout=AH.AH_LAYOUT_15)
 KERNELS = [AH.AH_KERNEL_PLAIN, AH.AH_KERNEL_TILED]
 SHAPES = [(64, 12, 10), (128, 6, 5)]
 
@@ -40,7 +46,7 @@ def _print_case(**kw):
 @pytest.mark.parametrize("prec", [AH.AH_FP64, AH.AH_FP32])
 def test_init_random_phase_matches_oracle(O, prec):
     _print_case(test="init", prec=prec)
-    p = AH.Params(32, 32, 32, precision=prec, seed=12345)
+    p = P15(32, 32, 32, precision=prec, seed=12345)
     t = AH.alloc_planes(p)
     with AH.Context([p], [t]) as c:
         got = fields_np(c)
@@ -60,7 +66,7 @@ def test_init_random_phase_matches_oracle(O, prec):
 def test_step_fp64_random_state(O, kernel, shape, era, s):
     _print_case(test="step_fp64", kernel=kernel, shape=shape, era=era, s=s)
     nx, ny, nz = shape
-    p = AH.Params(nx, ny, nz, precision=AH.AH_FP64, tau0=1.0, tau_ref=2.0, era_p=era, s=s,
+    p = P15(nx, ny, nz, precision=AH.AH_FP64, tau0=1.0, tau_ref=2.0, era_p=era, s=s,
                   init=AH.AH_INIT_NONE)
     st = I.random_state(shape, seed=101)
     op = oracle_params(O, p)
@@ -79,7 +85,7 @@ def test_step_fp32_random_state(O, kernel):
     1e-5 relative per field group after 10 steps."""
     shape = (64, 12, 10)
     _print_case(test="step_fp32", kernel=kernel, shape=shape)
-    p = AH.Params(*shape, precision=AH.AH_FP32, tau0=2.0, tau_ref=4.0, era_p=1.0, s=1.0,
+    p = P15(*shape, precision=AH.AH_FP32, tau0=2.0, tau_ref=4.0, era_p=1.0, s=1.0,
                   init=AH.AH_INIT_NONE)
     st = I.random_state(shape, seed=202).astype(np.float32).astype(np.float64)
     with _ctx(p, upload(p, st), kernel) as c:
@@ -115,7 +121,7 @@ def test_config_32cubed_fp64_run(O):
     """32^3, FP64, radiation, s = 1, random phase, 80 steps to tau = 8 with
     string length and <v^2> every 10 steps: every observable vs the oracle."""
     _print_case(test="c1_run")
-    p = AH.Params(32, 32, 32, precision=AH.AH_FP64, tau0=0.0, tau_ref=8.0, era_p=1.0, s=1.0,
+    p = P15(32, 32, 32, precision=AH.AH_FP64, tau0=0.0, tau_ref=8.0, era_p=1.0, s=1.0,
                   seed=1)
     op = oracle_params(O, p)
     with AH.Context([p], [AH.alloc_planes(p)]) as c:
@@ -137,7 +143,7 @@ def test_measure_and_wind_map_match_oracle(O, prec, kernel):
     by plaquette on identical input fields."""
     shape = (64, 10, 9)
     _print_case(test="measure", prec=prec, kernel=kernel)
-    p = AH.Params(*shape, precision=prec, tau0=3.0, tau_ref=4.0, era_p=2.0, s=0.0,
+    p = P15(*shape, precision=prec, tau0=3.0, tau_ref=4.0, era_p=2.0, s=0.0,
                   init=AH.AH_INIT_NONE, step0=7)
     st = I.random_state(shape, seed=303, amp_a=2.5)
     if prec == AH.AH_FP32:
@@ -189,7 +195,7 @@ def test_winding_near_link_boundaries(O, prec):
     oracle's at every plaquette whose links are not within 1e-9 of a tie."""
     shape = (64, 10, 9)
     _print_case(test="wind_near_boundaries", prec=prec)
-    p = AH.Params(*shape, precision=prec, tau0=3.0, tau_ref=4.0, era_p=2.0, s=0.0,
+    p = P15(*shape, precision=prec, tau0=3.0, tau_ref=4.0, era_p=2.0, s=0.0,
                   init=AH.AH_INIT_NONE, step0=7)
     st = I.random_state(shape, seed=515, amp_a=2.5)
     if prec == AH.AH_FP32:
@@ -216,7 +222,7 @@ def test_winding_near_link_boundaries(O, prec):
 def test_gauss_residual_matches_oracle(O, prec):
     shape = (64, 7, 6)
     _print_case(test="gauss", prec=prec)
-    p = AH.Params(*shape, precision=prec, tau0=2.0, tau_ref=3.0, era_p=1.0, s=0.5,
+    p = P15(*shape, precision=prec, tau0=2.0, tau_ref=3.0, era_p=1.0, s=0.5,
                   init=AH.AH_INIT_NONE, step0=4)
     st = I.random_state(shape, seed=404)
     if prec == AH.AH_FP32:
@@ -230,7 +236,7 @@ def test_gauss_residual_matches_oracle(O, prec):
 
 def test_nonfinite_is_reported():
     _print_case(test="nonfinite")
-    p = AH.Params(64, 8, 8, precision=AH.AH_FP32, init=AH.AH_INIT_VACUUM, tau0=1.0)
+    p = P15(64, 8, 8, precision=AH.AH_FP32, init=AH.AH_INIT_VACUUM, tau0=1.0)
     t = AH.alloc_planes(p)
     with AH.Context([p], [t]) as c:
         t[8, 3, 4, 5] = float("nan")
@@ -242,7 +248,7 @@ def test_nonfinite_is_reported():
 @pytest.mark.parametrize("prec", [AH.AH_FP64, AH.AH_FP32])
 def test_vacuum_stays_bitwise(prec):
     _print_case(test="vacuum", prec=prec)
-    p = AH.Params(64, 8, 8, precision=prec, init=AH.AH_INIT_VACUUM, tau0=0.0, tau_ref=2.0)
+    p = P15(64, 8, 8, precision=prec, init=AH.AH_INIT_VACUUM, tau0=0.0, tau_ref=2.0)
     with AH.Context([p], [AH.alloc_planes(p)]) as c:
         c.step(25)
         got = c.fields()
@@ -256,13 +262,13 @@ def test_checkpoint_resume_is_bitwise(prec):
     """Copy the state out at step 12, resume it in a fresh context with
     AH_INIT_NONE and step0 = 12: identical to the uninterrupted run."""
     _print_case(test="resume", prec=prec)
-    p = AH.Params(64, 16, 8, precision=prec, tau0=0.0, tau_ref=4.0, era_p=2.0, s=0.0, seed=9)
+    p = P15(64, 16, 8, precision=prec, tau0=0.0, tau_ref=4.0, era_p=2.0, s=0.0, seed=9)
     with AH.Context([p], [AH.alloc_planes(p)]) as c:
         c.step(12)
         mid = c.fields().clone()
         c.step(9)
         full = c.fields().clone()
-    q = AH.Params(**{**p.__dict__, "init": AH.AH_INIT_NONE, "step0": 12})
+    q = P15(**{**p.__dict__, "init": AH.AH_INIT_NONE, "step0": 12})
     t = AH.alloc_planes(q)
     t[:10] = mid
     with AH.Context([q], [t]) as c:
@@ -276,7 +282,7 @@ def test_context_on_its_own_stream():
     observations and winding map as one on the current stream; fields() and
     measure() order their copies after the library's work on that stream."""
     _print_case(test="own_stream")
-    p = AH.Params(128, 12, 10, precision=AH.AH_FP32, tau0=0.0, tau_ref=4.0, era_p=1.0, s=1.0,
+    p = P15(128, 12, 10, precision=AH.AH_FP32, tau0=0.0, tau_ref=4.0, era_p=1.0, s=1.0,
                   seed=19, layout=AH.AH_LAYOUT_20)
     side = torch.cuda.Stream()
     res = []
@@ -296,10 +302,10 @@ def test_batch_equals_solo_and_n_end():
     """Realizations of different sizes and eras in one context advance exactly
     as they do alone; a realization stops at its n_end."""
     _print_case(test="batch")
-    ps = [AH.Params(64, 8, 8, precision=AH.AH_FP32, tau_ref=2.0, era_p=1.0, s=1.0, seed=1),
-          AH.Params(64, 16, 4, precision=AH.AH_FP32, tau_ref=3.0, era_p=2.0, s=0.0, seed=2,
+    ps = [P15(64, 8, 8, precision=AH.AH_FP32, tau_ref=2.0, era_p=1.0, s=1.0, seed=1),
+          P15(64, 16, 4, precision=AH.AH_FP32, tau_ref=3.0, era_p=2.0, s=0.0, seed=2,
                     n_end=7),
-          AH.Params(128, 4, 6, precision=AH.AH_FP32, tau_ref=1.0, era_p=1.0, s=0.0, seed=3)]
+          P15(128, 4, 6, precision=AH.AH_FP32, tau_ref=1.0, era_p=1.0, s=0.0, seed=3)]
     with AH.Context(ps, [AH.alloc_planes(p) for p in ps]) as c:
         c.step(11)
         batch = [c.fields(r).clone() for r in range(3)]
@@ -314,7 +320,7 @@ def test_batch_equals_solo_and_n_end():
 def test_fused_schedule_matches_separate_measure(O):
     """ah_step's measurements equal ah_measure on the same states."""
     _print_case(test="fused_schedule")
-    p = AH.Params(64, 8, 8, precision=AH.AH_FP64, tau_ref=2.0, seed=4)
+    p = P15(64, 8, 8, precision=AH.AH_FP64, tau_ref=2.0, seed=4)
     with AH.Context([p], [AH.alloc_planes(p)]) as c:
         c.step(5)
         obs = c.step(10, measure_every=5)
@@ -337,7 +343,7 @@ def test_tiling_invariance_is_bitwise(prec):
     _print_case(test="tiling", prec=prec, shape=shape)
     tys = [2, 4, 8] + ([16] if prec == AH.AH_FP32 else [])
     configs = [(ty, cz) for ty in tys for cz in (0, 1, 5, 13)]
-    p = AH.Params(*shape, precision=prec, tau0=1.0, tau_ref=3.0, era_p=1.0, s=1.0,
+    p = P15(*shape, precision=prec, tau0=1.0, tau_ref=3.0, era_p=1.0, s=1.0,
                   init=AH.AH_INIT_NONE)
     st = I.random_state(shape, seed=505)
     ref = None
@@ -355,7 +361,7 @@ def test_fused_measurement_run_matches_oracle(O):
     """FP64, 64x24x20, radiation s=1 from the random-phase start: 40 steps with
     the diagnostics fused into the tiled step kernel every 10 steps."""
     _print_case(test="fused_run")
-    p = AH.Params(64, 24, 20, precision=AH.AH_FP64, tau0=0.0, tau_ref=5.0, era_p=1.0, s=1.0,
+    p = P15(64, 24, 20, precision=AH.AH_FP64, tau0=0.0, tau_ref=5.0, era_p=1.0, s=1.0,
                   seed=11)
     op = oracle_params(O, p)
     with _ctx(p, AH.alloc_planes(p), AH.AH_KERNEL_TILED) as c:
@@ -374,7 +380,7 @@ def test_fused_measurement_on_identical_input(O, prec):
     measurement of the same (widened) state."""
     shape = (128, 12, 10)
     _print_case(test="fused_identical", prec=prec)
-    p = AH.Params(*shape, precision=prec, tau0=1.0, tau_ref=3.0, era_p=2.0, s=0.0, seed=21)
+    p = P15(*shape, precision=prec, tau0=1.0, tau_ref=3.0, era_p=2.0, s=0.0, seed=21)
     with _ctx(p, AH.alloc_planes(p), AH.AH_KERNEL_TILED) as c:
         c.step(10)
         st = fields_np(c)
@@ -395,10 +401,10 @@ def test_fused_measurement_on_identical_input(O, prec):
 
 def _ensemble(prec=AH.AH_FP32):
     """Uneven realizations, mixed eras and s, one stopping early (n_end)."""
-    return [AH.Params(64, 8, 8, precision=prec, tau_ref=2.0, era_p=1.0, s=1.0, seed=31),
-            AH.Params(128, 16, 12, precision=prec, tau_ref=3.0, era_p=2.0, s=0.0, seed=32),
-            AH.Params(64, 24, 20, precision=prec, tau_ref=2.5, era_p=1.0, s=0.0, seed=33, n_end=9),
-            AH.Params(192, 6, 5, precision=prec, tau_ref=1.5, era_p=2.0, s=0.0, seed=34)]
+    return [P15(64, 8, 8, precision=prec, tau_ref=2.0, era_p=1.0, s=1.0, seed=31),
+            P15(128, 16, 12, precision=prec, tau_ref=3.0, era_p=2.0, s=0.0, seed=32),
+            P15(64, 24, 20, precision=prec, tau_ref=2.5, era_p=1.0, s=0.0, seed=33, n_end=9),
+            P15(192, 6, 5, precision=prec, tau_ref=1.5, era_p=2.0, s=0.0, seed=34)]
 
 
 def _run_ensemble(ps, batched, graph_steps, nsteps=17, measure_every=5):
@@ -483,7 +489,7 @@ def test_core_growth_switch_matches_oracle(O, kernel):
     fields and measurements across the switch against the oracle."""
     shape = (64, 12, 10)
     _print_case(test="core_growth", kernel=kernel)
-    p = AH.Params(*shape, precision=AH.AH_FP64, tau0=0.5, tau_ref=1.5, era_p=1.0, s=-1.0,
+    p = P15(*shape, precision=AH.AH_FP64, tau0=0.5, tau_ref=1.5, era_p=1.0, s=-1.0,
                   s_late=1.0, tau_s=1.5, seed=61)
     op = oracle_params(O, p)
     with _ctx(p, AH.alloc_planes(p), kernel) as c:

@@ -37,7 +37,8 @@ def _reference(shapes, prec, steps):
     """Realizations from the seeded random phase advanced `steps` single steps
     (even: the state is back in planes 0-9), and ah_measure of them."""
     ps = [AH.Params(nx, ny, nz, precision=prec, tau0=0.0, tau_ref=4.0, era_p=1.0 + (k % 2),
-                    s=1.0 - (k % 2), seed=50 + k) for k, (nx, ny, nz) in enumerate(shapes)]
+                    s=1.0 - (k % 2), seed=50 + k, layout=AH.AH_LAYOUT_15)
+          for k, (nx, ny, nz) in enumerate(shapes)]
     planes = [AH.alloc_planes(p) for p in ps]
     ctx = AH.Context(ps, planes)
     ctx.step(steps)
