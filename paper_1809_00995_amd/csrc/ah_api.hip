@@ -274,10 +274,10 @@ int batch_ty(const ah_ctx *c) {
     return std::min(ty, tiled_ty_max(fp64, MODE_STEP_MEASURE));
 }
 
-int launch_tiled(ah_ctx *c, int r, int mode, Slot *slot, int8_t *wind) {
+int launch_tiled(ah_ctx *c, int r, int mode, Slot *slot) {
     const ah_params &q = c->p[r];
     int rc = launch_step_tiled(c->prec == AH_FP64, mode, c->d_desc, c->d_coef, r, q.nx, q.ny, q.nz,
-                               c->tile_y, c->cz[r], slot, wind, c->stream);
+                               c->tile_y, c->cz[r], slot, c->stream);
     if (rc)
         return fail(c, AH_E_HIP, "tiled kernel launch (mode %d) failed: %s", mode,
                     hipGetErrorString((hipError_t)rc));
@@ -301,7 +301,7 @@ int launch_measure_plain(ah_ctx *c, int r, Slot *slot, int8_t *wind) {
 // device); with slot != NULL also measure the state it reads into slot.
 int launch_step(ah_ctx *c, int r, Slot *slot) {
     if (use_tiled(c, r))
-        return launch_tiled(c, r, slot ? MODE_STEP_MEASURE : MODE_STEP, slot, nullptr);
+        return launch_tiled(c, r, slot ? MODE_STEP_MEASURE : MODE_STEP, slot);
     if (slot)
         TRY(launch_measure_plain(c, r, slot, nullptr));
     const int64_t N = sites_of(c->p[r]);
@@ -316,9 +316,15 @@ int launch_step(ah_ctx *c, int r, Slot *slot) {
 
 // Measure the current state of realization r into slot (standalone pass).
 int launch_measure(ah_ctx *c, int r, Slot *slot, int8_t *wind) {
-    if (use_tiled(c, r))
-        return launch_tiled(c, r, MODE_MEASURE, slot, wind);
-    return launch_measure_plain(c, r, slot, wind);
+    if (!use_tiled(c, r))
+        return launch_measure_plain(c, r, slot, wind);
+    const ah_params &q = c->p[r];
+    int rc = launch_measure_tiled(c->prec == AH_FP64, c->d_desc, c->d_coef, r, q.nx, q.ny, q.nz,
+                                  c->tile_y, c->cz[r], slot, wind, c->stream);
+    if (rc)
+        return fail(c, AH_E_HIP, "measuring kernel launch failed: %s",
+                    hipGetErrorString((hipError_t)rc));
+    return AH_OK;
 }
 
 int launch_finalize(ah_ctx *c, int64_t nslots) {
@@ -915,8 +921,8 @@ int ah_measure_noalloc(int32_t n_real, const ah_params *p, const ah_buffers *buf
         const ah_params &q = p[r];
         int8_t *w = wind_dev ? wind_dev + off : nullptr;
         if (q.nx % 64 == 0) {
-            int rc = launch_step_tiled(fp64, MODE_MEASURE, descs, coefs, r, q.nx, q.ny, q.nz, 0, 0,
-                                       slots + r, w, st);
+            int rc = launch_measure_tiled(fp64, descs, coefs, r, q.nx, q.ny, q.nz, 0, 0, slots + r,
+                                          w, st);
             if (rc)
                 return fail(nullptr, AH_E_HIP, "tiled measuring kernel launch failed: %s",
                             hipGetErrorString((hipError_t)rc));
@@ -1170,7 +1176,7 @@ int ah_autotune(ah_ctx *c, int32_t *tile_y, int32_t *chunk_z) {
                                                                      c->stream)
                                                  : launch_step_tiled(fp64, MODE_STEP, d_desc, d_coef,
                                                                      0, sh.nx, sh.ny, nzs, t, z,
-                                                                     nullptr, nullptr, c->stream)),
+                                                                     nullptr, c->stream)),
                                "tiled launch");
                     }
                     float ms = 0.f;

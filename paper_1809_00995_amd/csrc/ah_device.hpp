@@ -52,9 +52,12 @@ struct Coef {
 };
 
 // Raw per-measurement accumulators (sums over sites, before the dx^3 factor).
+// The sum of the pressure is linear in the five parts of the energy density
+// and is formed from their sums; the Lagrangian, a difference of those parts
+// that can be much smaller than each, is summed site by site.
 enum : int { A_KIN, A_GRAD, A_ELEC, A_MAG, A_POT, A_LAG,
              A_NUM_L, A_NUM_V, A_NUM_R, A_DEN_L, A_DEN_V, A_DEN_R,
-             A_PRES, A_PRES_L, A_RHO_L, A_COUNT };
+             A_PRES_L, A_RHO_L, A_COUNT };
 enum : int { C_W0, C_W1, C_W2, C_N0, C_N1, C_N2, C_PIERCED, C_NONFIN, C_COUNT };
 
 struct Acc {

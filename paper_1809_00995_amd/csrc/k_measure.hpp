@@ -117,7 +117,6 @@ k_measure_plain(const RealDesc *descs, const Coef *coefs, int r, Slot *slot, int
         v[A_DEN_L] += G * lag;
         v[A_DEN_V] += G * V;
         v[A_DEN_R] += G * rho;
-        v[A_PRES] += pres;
         v[A_PRES_L] += pres * lag;
         v[A_RHO_L] += rho * lag;
 
@@ -236,16 +235,17 @@ __global__ void k_finalize(const RealDesc *descs, const Slot *slots, ah_obs *out
     o.nonfinite = (int64_t)sl.acc.c[C_NONFIN];
     o.length = (kPi / 6.0) * d.dx * (double)o.n_wind;
     o.xi_w = sqrt(vbox / o.length);
-    o.sum_lag = dv * sl.acc.s[A_LAG];
-    o.xi_l = o.sum_lag < 0.0 ? o.a * sqrt(-(kTwoPi * d.sigma * d.sigma) * vbox / o.sum_lag)
-                             : __builtin_nan("");
     o.kin = dv * sl.acc.s[A_KIN];
     o.grad = dv * sl.acc.s[A_GRAD];
     o.elec = dv * sl.acc.s[A_ELEC];
     o.mag = dv * sl.acc.s[A_MAG];
     o.pot = dv * sl.acc.s[A_POT];
     o.energy = o.kin + o.grad + o.elec + o.mag + o.pot;
-    o.pres = dv * sl.acc.s[A_PRES];
+    // p = a^2 K - a^2 G/3 + g (EE + BB)/3 - h V
+    o.sum_lag = dv * sl.acc.s[A_LAG];
+    o.xi_l = o.sum_lag < 0.0 ? o.a * sqrt(-(kTwoPi * d.sigma * d.sigma) * vbox / o.sum_lag)
+                             : __builtin_nan("");
+    o.pres = o.kin - o.grad / 3.0 + (o.elec + o.mag) / 3.0 - o.pot;
     o.pres_lag = dv * sl.acc.s[A_PRES_L];
     o.rho_lag = dv * sl.acc.s[A_RHO_L];
     o.v2_eos = 0.5 * (1.0 + 3.0 * o.pres_lag / o.rho_lag);   // Eq. (12)

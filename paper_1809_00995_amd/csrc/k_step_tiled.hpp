@@ -20,13 +20,16 @@
 //    the halo reads of adjacent tiles meet in the same L2.
 //
 // Modes: MODE_STEP advances S_n -> S_{n+1}; MODE_STEP_MEASURE also measures
-// S_n (the state it reads) on the way; MODE_MEASURE only measures (and can
-// write the per-plaquette winding map).  The measuring modes stage arg(phi)
-// in FP64 and the raw link angles A_i next to the phasors, and count the
-// winding of each plaquette from the wrap counts of its four links:
-// with m_i(s) = floor((theta(s+i) - theta(s) + A_i(s) + pi) / 2 pi) the
-// [.]_pi of Eq. (11) subtracts 2 pi m_i, the phase differences cancel around
-// the plaquette, and W_ij = -(m_i(x) + m_j(x+i) - m_i(x+j) - m_j(x)) exactly.
+// S_n (the state it reads) on the way (the read-only measuring pass is
+// k_measure_tiled.hpp).  The measuring mode stages arg(phi) in FP32 and the
+// raw link angles A_i next to the phasors, and counts the winding of each
+// plaquette from the wrap counts of its four links: with
+// m_i(s) = floor((theta(s+i) - theta(s) + A_i(s) + pi) / 2 pi) the [.]_pi of
+// Eq. (11) subtracts 2 pi m_i, the phase differences cancel around the
+// plaquette, and W_ij = -(m_i(x) + m_j(x+i) - m_i(x+j) - m_j(x)) exactly.
+// Each in-plane link's count is formed once, by the thread that stages its
+// site, one plane ahead, and shared through LDS; a site forms the z-link
+// counts of itself and of its x and y neighbours.
 #pragma once
 
 #include <type_traits>
@@ -35,7 +38,7 @@
 
 namespace ah {
 
-enum : int { MODE_STEP = 0, MODE_STEP_MEASURE = 1, MODE_MEASURE = 2 };
+enum : int { MODE_STEP = 0, MODE_STEP_MEASURE = 1 };
 
 // quantities staged per site in LDS
 enum : int { Q_PR, Q_PI, Q_UXC, Q_UXS, Q_UYC, Q_UYS, Q_UZC, Q_UZS, Q_COUNT };
@@ -45,7 +48,18 @@ template <int TY> struct TileGeom {
     static constexpr int H = TY + 2;
     static constexpr int S = W * H;
     static constexpr int HALO = 2 * 64 + 2 * H;   // halo ring, corners included
+    static constexpr int HALO_FWD = 65 + TY;      // the row above (with its right end) and
+                                                  // the column to the right
     static __device__ __forceinline__ int li(int lx, int ly) { return (ly + 1) * W + (lx + 1); }
+    static __device__ __forceinline__ void halo_fwd(int h, int &lx, int &ly) {
+        if (h < 65) {
+            lx = h;
+            ly = TY;
+        } else {
+            lx = 64;
+            ly = h - 65;
+        }
+    }
     static __device__ __forceinline__ void halo(int h, int &lx, int &ly) {
         if (h < 64) {
             lx = h;
@@ -97,22 +111,37 @@ __device__ __forceinline__ int wrap_count(double u) {
     return (int)floor((u + kPi) * kInvTwoPi);
 }
 
-// The measuring kernels decide wrap counts on FP32 phases (phase_f32, error
-// below 5e-7) and fall back to FP64 phases (atan2) for every link of a site
-// when any of its quotients (u + pi) / 2 pi lies within kWrapMargin of an
-// integer: the two sets of phases move a quotient by at most ~1.6e-7, so
-// outside the margin both give the same integer, and the counts equal those
-// of FP64 phases everywhere.
-constexpr double kWrapMargin = 4e-6;
+// The measuring kernels take each wrap count from FP32 phases (phase_f32,
+// error below 5e-7) in FP32 arithmetic: ta, tb are the phases at the start and
+// end of the link and a its raw angle.  False when the FP64 phases (atan2)
+// must decide instead: the quotient (u + pi) / 2 pi within the margin of an
+// integer, a phase not a number, or |a| > 32.  For |a| <= 32 the four
+// roundings move the quotient by at most 1.3e-6 and the phase errors by
+// 1.6e-7 more, so outside the margin the integer is the one FP64 phases give.
+constexpr float kWrapMarginF = 4e-6f;
 
-// m = wrap_count(u) from FP32 phases; false when the FP64 phases must decide
-// (u within the margin of a boundary, or not a number).
-__device__ __forceinline__ bool wrap_count_sure(double u, int &m) {
-    const double w = (u + kPi) * kInvTwoPi;
-    const double f = floor(w);
+__device__ __forceinline__ bool wrap_count_f32(float ta, float tb, float a, int &m) {
+    const float u = (tb - ta) + a;
+    const float w = (u + 3.1415927e+00f) * 1.5915494e-01f;
+    const float f = __builtin_floorf(w);
     m = (int)f;
-    const double fr = w - f;
-    return fr > kWrapMargin && fr < 1.0 - kWrapMargin;
+    const float fr = w - f;
+    return fr > kWrapMarginF && fr < 1.0f - kWrapMarginF && __builtin_fabsf(a) <= 32.0f;
+}
+
+// FP64 phase of phi = (pr, pi), as the oracle takes it.
+template <typename T> __device__ __forceinline__ double phase64(T pr, T pi) {
+    return atan2((double)pi, (double)pr);
+}
+
+// Wrap count of one link from the FP32 phases ta, tb of its ends and its raw
+// angle a; dphase() gives the FP64 phase difference when those must decide.
+template <typename T, typename F>
+__device__ __forceinline__ int wrap_count_link(float ta, float tb, T a, F dphase) {
+    int m;
+    if (!wrap_count_f32(ta, tb, (float)a, m))
+        m = wrap_count(dphase() + (double)a);
+    return m;
 }
 
 template <typename T> struct SiteV {
@@ -223,118 +252,82 @@ __device__ __forceinline__ void meas_init(MeasAcc &m, const RealDesc &d, const C
     m.s2 = d.sigma * d.sigma;
 }
 
-// What the measurement of site x reads: its fields and phasors, phi at
-// x+x, x+y, x+z, the phasors of the other links of its three forward
-// plaquettes, and the FP32 phases of phi and the raw link angles at the
-// corners of those plaquettes.
+// What the densities of site x read: its fields and phasors, phi at x+x,
+// x+y, x+z, and the phasors of the other links of its three forward
+// plaquettes.
 template <typename T> struct MeasSite {
     T pr, pm, pr0, pi0, ax, ay, az, ex0, ey0, ez0;
     T uxc, uxs, uyc, uys, uzc, uzs;
     T pr_xp, pi_xp, pr_yp, pi_yp, pr_zp, pi_zp;
     T uyc_xp, uys_xp, uzc_xp, uzs_xp, uxc_yp, uxs_yp, uzc_yp, uzs_yp, uxc_zp, uxs_zp, uyc_zp, uys_zp;
-    float th, th_xp, th_yp, th_xpyp, th_zp, th_xpzp, th_ypzp;
-    double ay_xp, az_xp, ax_yp, az_yp, ax_zp, ay_zp;
 };
 
-// phi at the corners x+x+y, x+x+z, x+y+z of the forward plaquettes (read
-// only when the winding falls back to FP64 phases).
-template <typename T> struct Corners {
-    T pr_xpyp, pi_xpyp, pr_xpzp, pi_xpzp, pr_ypzp, pi_ypzp;
-};
-
-// Add site x of S_n to the accumulators: the densities of Eqs. (9)-(10), the
-// pressure of Eq. (12), and the windings of its xy, yz, zx plaquettes
-// (Eq. (11)) from the wrap counts of their links; w3 receives the windings.
-// corners() returns the Corners of the site.
-template <typename T, typename CornersFn>
-__device__ __forceinline__ void measure_site(MeasAcc &m, const MeasSite<T> &v, int (&w3)[3],
-                                             CornersFn corners) {
+// Add site x of S_n to the accumulators: the densities of Eqs. (9)-(10) and
+// the pressure of Eq. (12), formed in the storage precision T and summed in
+// FP64.  Returns false (and counts the site) when a field is not finite.
+// The pressure is linear in the five parts of the energy density, so its sum
+// is formed from theirs when the measurement is finalised.
+template <typename T>
+__device__ __forceinline__ bool measure_densities(MeasAcc &m, const MeasSite<T> &v) {
+    // every multiply-add written out and contraction off: the per-site values
+    // are bitwise the same in every kernel that measures (the fused measuring
+    // step, the read-only pass, the batched kernel)
+#pragma clang fp contract(off)
     const bool finite = __builtin_isfinite(v.pr) && __builtin_isfinite(v.pm) &&
                         __builtin_isfinite(v.pr0) && __builtin_isfinite(v.pi0) &&
                         __builtin_isfinite(v.ax) && __builtin_isfinite(v.ay) &&
                         __builtin_isfinite(v.az) && __builtin_isfinite(v.ex0) &&
                         __builtin_isfinite(v.ey0) && __builtin_isfinite(v.ez0);
-    w3[0] = w3[1] = w3[2] = 0;
     if (!finite) {
         m.c[C_NONFIN] += 1;
-        return;
+        return false;
     }
     const T pr = v.pr, pm = v.pm;
-    const T gxr = v.uxc * v.pr_xp - v.uxs * v.pi_xp - pr;
-    const T gxi = v.uxc * v.pi_xp + v.uxs * v.pr_xp - pm;
-    const T gyr = v.uyc * v.pr_yp - v.uys * v.pi_yp - pr;
-    const T gyi = v.uyc * v.pi_yp + v.uys * v.pr_yp - pm;
-    const T gzr = v.uzc * v.pr_zp - v.uzs * v.pi_zp - pr;
-    const T gzi = v.uzc * v.pi_zp + v.uzs * v.pr_zp - pm;
-    const double idx2 = m.idx2, ma2 = m.a2, mg = m.g, mh = m.h;
-    const double K = (double)v.pr0 * v.pr0 + (double)v.pi0 * v.pi0;
-    const double Gr = idx2 * ((double)gxr * gxr + (double)gxi * gxi + (double)gyr * gyr +
-                              (double)gyi * gyi + (double)gzr * gzr + (double)gzi * gzi);
-    const double EE = idx2 * ((double)v.ex0 * v.ex0 + (double)v.ey0 * v.ey0 + (double)v.ez0 * v.ez0);
+    // e^{iA_i} phi(x+i) - phi(x)
+    const T gxr = fma(v.uxc, v.pr_xp, fma(-v.uxs, v.pi_xp, -pr));
+    const T gxi = fma(v.uxc, v.pi_xp, fma(v.uxs, v.pr_xp, -pm));
+    const T gyr = fma(v.uyc, v.pr_yp, fma(-v.uys, v.pi_yp, -pr));
+    const T gyi = fma(v.uyc, v.pi_yp, fma(v.uys, v.pr_yp, -pm));
+    const T gzr = fma(v.uzc, v.pr_zp, fma(-v.uzs, v.pi_zp, -pr));
+    const T gzi = fma(v.uzc, v.pi_zp, fma(v.uzs, v.pr_zp, -pm));
+    const T idx2 = (T)m.idx2, a2 = (T)m.a2, g = (T)m.g, h = (T)m.h;
+    const T K = fma(v.pr0, v.pr0, v.pi0 * v.pi0);
+    const T gs = fma(gxr, gxr, fma(gxi, gxi, fma(gyr, gyr, fma(gyi, gyi, fma(gzr, gzr, gzi * gzi)))));
+    const T Gr = idx2 * gs;
+    const T EE = idx2 * fma(v.ex0, v.ex0, fma(v.ey0, v.ey0, v.ez0 * v.ez0));
     const T oxy = plaq_omc(v.uxc, v.uxs, v.uyc_xp, v.uys_xp, v.uxc_yp, v.uxs_yp, v.uyc, v.uys);
     const T oyz = plaq_omc(v.uyc, v.uys, v.uzc_yp, v.uzs_yp, v.uyc_zp, v.uys_zp, v.uzc, v.uzs);
     const T ozx = plaq_omc(v.uzc, v.uzs, v.uxc_zp, v.uxs_zp, v.uzc_xp, v.uzs_xp, v.uxc, v.uxs);
-    const double BB = 2.0 * idx2 * idx2 * ((double)oxy + (double)oyz + (double)ozx);
-    const double vv = (double)pr * pr + (double)pm * pm - m.s2;
-    const double V = 0.25 * vv * vv;
-    const double lag = ma2 * K - ma2 * Gr + mg * (EE - BB) - mh * V;
-    const double rho = ma2 * K + ma2 * Gr + mg * (EE + BB) + mh * V;
-    // the thirds as products with 1/3 (two FP64 divisions per site saved; the
-    // results differ from the quotients by at most an ulp of each term)
-    constexpr double kThird = 1.0 / 3.0;
-    const double pres = ma2 * K - (ma2 * Gr) * kThird + (mg * (EE + BB)) * kThird - mh * V;
-    m.s[A_KIN] += ma2 * K;
-    m.s[A_GRAD] += ma2 * Gr;
-    m.s[A_ELEC] += mg * EE;
-    m.s[A_MAG] += mg * BB;
-    m.s[A_POT] += mh * V;
-    m.s[A_LAG] += lag;
-    m.s[A_NUM_L] += K * lag;
-    m.s[A_NUM_V] += K * V;
-    m.s[A_NUM_R] += K * rho;
-    m.s[A_DEN_L] += Gr * lag;
-    m.s[A_DEN_V] += Gr * V;
-    m.s[A_DEN_R] += Gr * rho;
-    m.s[A_PRES] += pres;
-    m.s[A_PRES_L] += pres * lag;
-    m.s[A_RHO_L] += rho * lag;
+    const T BB = ((T)2 * idx2 * idx2) * ((oxy + oyz) + ozx);
+    // |phi|^2 - sigma^2 in FP64: near the vacuum it is a small difference of
+    // numbers near sigma^2, which the storage precision would not resolve
+    const double vv = fma((double)pr, (double)pr, fma((double)pm, (double)pm, -m.s2));
+    const T V = (T)(0.25 * (vv * vv));
+    const T kin = a2 * K, grad = a2 * Gr, elec = g * EE, mag = g * BB, pot = h * V;
+    const T lag = ((kin - grad) + (elec - mag)) - pot;
+    const T rho = ((kin + grad) + (elec + mag)) + pot;
+    const T third = (T)(1.0 / 3.0);
+    const T pres = fma(elec + mag, third, fma(-grad, third, kin)) - pot;
+    m.s[A_KIN] += (double)kin;
+    m.s[A_GRAD] += (double)grad;
+    m.s[A_ELEC] += (double)elec;
+    m.s[A_MAG] += (double)mag;
+    m.s[A_POT] += (double)pot;
+    m.s[A_LAG] += (double)lag;
+    m.s[A_NUM_L] += (double)(K * lag);
+    m.s[A_NUM_V] += (double)(K * V);
+    m.s[A_NUM_R] += (double)(K * rho);
+    m.s[A_DEN_L] += (double)(Gr * lag);
+    m.s[A_DEN_V] += (double)(Gr * V);
+    m.s[A_DEN_R] += (double)(Gr * rho);
+    m.s[A_PRES_L] += (double)(pres * lag);
+    m.s[A_RHO_L] += (double)(rho * lag);
+    return true;
+}
 
-    // winding (Eq. (11)) from link wrap counts: FP32 phases, FP64 near a boundary
-    const double ax = v.ax, ay = v.ay, az = v.az;
-    const double t = v.th, t_xp = v.th_xp, t_yp = v.th_yp, t_zp = v.th_zp;
-    const double t_xpyp = v.th_xpyp, t_xpzp = v.th_xpzp, t_ypzp = v.th_ypzp;
-    int mx, my, mz, my_xp, mx_yp, mz_yp, my_zp, mx_zp, mz_xp;
-    bool sure = wrap_count_sure(t_xp - t + ax, mx);
-    sure &= wrap_count_sure(t_yp - t + ay, my);
-    sure &= wrap_count_sure(t_zp - t + az, mz);
-    sure &= wrap_count_sure(t_xpyp - t_xp + v.ay_xp, my_xp);
-    sure &= wrap_count_sure(t_xpyp - t_yp + v.ax_yp, mx_yp);
-    sure &= wrap_count_sure(t_ypzp - t_yp + v.az_yp, mz_yp);
-    sure &= wrap_count_sure(t_ypzp - t_zp + v.ay_zp, my_zp);
-    sure &= wrap_count_sure(t_xpzp - t_zp + v.ax_zp, mx_zp);
-    sure &= wrap_count_sure(t_xpzp - t_xp + v.az_xp, mz_xp);
-    if (!sure) {
-        const Corners<T> k = corners();
-        const double e = atan2((double)v.pm, (double)v.pr);
-        const double e_xp = atan2((double)v.pi_xp, (double)v.pr_xp);
-        const double e_yp = atan2((double)v.pi_yp, (double)v.pr_yp);
-        const double e_zp = atan2((double)v.pi_zp, (double)v.pr_zp);
-        const double e_xpyp = atan2((double)k.pi_xpyp, (double)k.pr_xpyp);
-        const double e_xpzp = atan2((double)k.pi_xpzp, (double)k.pr_xpzp);
-        const double e_ypzp = atan2((double)k.pi_ypzp, (double)k.pr_ypzp);
-        mx = wrap_count(e_xp - e + ax);
-        my = wrap_count(e_yp - e + ay);
-        mz = wrap_count(e_zp - e + az);
-        my_xp = wrap_count(e_xpyp - e_xp + v.ay_xp);
-        mx_yp = wrap_count(e_xpyp - e_yp + v.ax_yp);
-        mz_yp = wrap_count(e_ypzp - e_yp + v.az_yp);
-        my_zp = wrap_count(e_ypzp - e_zp + v.ay_zp);
-        mx_zp = wrap_count(e_xpzp - e_zp + v.ax_zp);
-        mz_xp = wrap_count(e_xpzp - e_xp + v.az_xp);
-    }
-    w3[0] = -(mx + my_xp - mx_yp - my);
-    w3[1] = -(my + mz_yp - my_zp - mz);
-    w3[2] = -(mz + mx_zp - mz_xp - mx);
+// Add the windings of the three forward plaquettes of a site (Eq. (11)) to
+// the counters.
+__device__ __forceinline__ void count_windings(MeasAcc &m, const int (&w3)[3]) {
     for (int k = 0; k < 3; ++k) {
         m.c[C_W0 + k] += w3[k];
         m.c[C_N0 + k] += w3[k] < 0 ? -w3[k] : w3[k];
@@ -371,14 +364,14 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // it with the same arguments.
 template <typename T, int TY, int MODE>
 __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int tile, int cz,
-                                           Slot *slot, int8_t *wind) {
+                                           Slot *slot) {
     constexpr bool MEAS = MODE != MODE_STEP;
-    constexpr bool UPD = MODE != MODE_MEASURE;
     using G = TileGeom<TY>;
     constexpr int SM = MEAS ? G::S : 1;
     __shared__ T lds[2][Q_COUNT][G::S];
     __shared__ float lth[2][SM];       // FP32 phase of phi (measuring modes)
     __shared__ T lar[2][3][SM];        // raw link angles (measuring modes)
+    __shared__ int lcnt[2][2][SM];     // wrap counts of the x and y links (measuring modes)
 
     const int nx = d.nx, ny = d.ny, nz = d.nz;
     const int ntx = nx >> 6, nty = (ny + TY - 1) / TY;
@@ -456,6 +449,44 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
     };
     auto own = [&](int z) { return gx + nx * (gy + ny * z); };
 
+    // Wrap count of the link from LDS site ka to kb (same buffer bf) with raw
+    // angle a: FP32 phases, FP64 phases when the quotient is too close to call.
+    auto link_count = [&](int bf, int ka, int kb, T a) {
+        int m;
+        if (!wrap_count_f32(lth[bf][ka], lth[bf][kb], (float)a, m))
+            m = wrap_count(phase64(lds[bf][Q_PR][kb], lds[bf][Q_PI][kb]) -
+                           phase64(lds[bf][Q_PR][ka], lds[bf][Q_PI][ka]) + (double)a);
+        return m;
+    };
+    // In-plane wrap counts of plane buffer bf: this thread's own site (x and y
+    // links, raw angles ax, ay) and the halo sites it staged whose links the
+    // tile's plaquettes use (the x link of the row above, the y link of the
+    // column to the right).  Returns the own counts.
+    auto plane_counts = [&](int bf, T ax, T ay, int &mx, int &my) {
+        int cx, cy;
+        const bool sx = wrap_count_f32(lth[bf][q], lth[bf][q + 1], (float)ax, cx);
+        const bool sy = wrap_count_f32(lth[bf][q], lth[bf][q + G::W], (float)ay, cy);
+        if (!(sx && sy)) {
+            const double e = phase64(lds[bf][Q_PR][q], lds[bf][Q_PI][q]);
+            cx = wrap_count(phase64(lds[bf][Q_PR][q + 1], lds[bf][Q_PI][q + 1]) - e + (double)ax);
+            cy = wrap_count(phase64(lds[bf][Q_PR][q + G::W], lds[bf][Q_PI][q + G::W]) - e +
+                            (double)ay);
+        }
+        lcnt[bf][0][q] = cx;
+        lcnt[bf][1][q] = cy;
+        mx = cx;
+        my = cy;
+        for (int h = t; h < G::HALO; h += 64 * TY) {
+            int hx, hy;
+            G::halo(h, hx, hy);
+            const int k = G::li(hx, hy);
+            if (hy == TY && hx >= 0 && hx < 64)
+                lcnt[bf][0][k] = link_count(bf, k, k + 1, lar[bf][0][k]);
+            else if (hx == 64 && hy >= 0 && hy < TY)
+                lcnt[bf][1][k] = link_count(bf, k, k + G::W, lar[bf][1][k]);
+        }
+    };
+
     // prologue: planes z0-1 (buffer 1) and z0 (buffer 0); z below is
     // slab-relative, zmap gives the stored plane
     const int zm0 = zmap(d, z0 - 1), zc0 = zmap(d, z0);
@@ -473,6 +504,10 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
     T pzx_m = plaq_sin(prv.uzc, prv.uzs, cur.uxc, cur.uxs, lds[1][Q_UZC][q + 1],
                        lds[1][Q_UZS][q + 1], prv.uxc, prv.uxs);
     T phr_m = prv.pr, phi_m = prv.pm, uzc_m = prv.uzc, uzs_m = prv.uzs;
+    // wrap counts of the in-plane links of plane z0
+    int mx_c = 0, my_c = 0;
+    if (MEAS)
+        plane_counts(0, cur.ax, cur.ay, mx_c, my_c);
     __syncthreads();
 
     for (int z = z0; z < z1; ++z) {
@@ -521,7 +556,7 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
         const T pzx_xm = plaq_sin(uzc_xm, uzs_xm, uxc_xmzp, uxs_xmzp, cur.uzc, cur.uzs, uxc_xm, uxs_xm);
 
         const T pr = cur.pr, pm = cur.pm;
-        if (UPD) {
+        {
             Stencil<T> st;
             st.pr = pr; st.pm = pm; st.ax = cur.ax; st.ay = cur.ay; st.az = cur.az;
             st.uxc = cur.uxc; st.uxs = cur.uxs; st.uyc = cur.uyc; st.uys = cur.uys;
@@ -551,39 +586,49 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
             }
         }
 
-        if (MEAS && owner) {
-            // Eqs. (9)-(12) for the site of S_n read above
-            MeasSite<T> mv;
-            mv.pr = pr; mv.pm = pm; mv.pr0 = pr0; mv.pi0 = pi0;
-            mv.ax = cur.ax; mv.ay = cur.ay; mv.az = cur.az;
-            mv.ex0 = ex0; mv.ey0 = ey0; mv.ez0 = ez0;
-            mv.uxc = cur.uxc; mv.uxs = cur.uxs; mv.uyc = cur.uyc; mv.uys = cur.uys;
-            mv.uzc = cur.uzc; mv.uzs = cur.uzs;
-            mv.pr_xp = pr_xp; mv.pi_xp = pi_xp; mv.pr_yp = pr_yp; mv.pi_yp = pi_yp;
-            mv.pr_zp = nxt.pr; mv.pi_zp = nxt.pm;
-            mv.uyc_xp = uyc_xp; mv.uys_xp = uys_xp; mv.uzc_xp = uzc_xp; mv.uzs_xp = uzs_xp;
-            mv.uxc_yp = uxc_yp; mv.uxs_yp = uxs_yp; mv.uzc_yp = uzc_yp; mv.uzs_yp = uzs_yp;
-            mv.uxc_zp = nxt.uxc; mv.uxs_zp = nxt.uxs; mv.uyc_zp = nxt.uyc; mv.uys_zp = nxt.uys;
-            mv.th = cur.th; mv.th_xp = lth[cb][q + 1]; mv.th_yp = lth[cb][q + G::W];
-            mv.th_xpyp = lth[cb][q + 1 + G::W];
-            mv.th_zp = nxt.th; mv.th_xpzp = lth[nb_][q + 1]; mv.th_ypzp = lth[nb_][q + G::W];
-            mv.ay_xp = lar[cb][1][q + 1]; mv.az_xp = lar[cb][2][q + 1];
-            mv.ax_yp = lar[cb][0][q + G::W]; mv.az_yp = lar[cb][2][q + G::W];
-            mv.ax_zp = nxt.ax; mv.ay_zp = nxt.ay;
-            int w3[3];
-            measure_site(macc, mv, w3, [&]() {
-                Corners<T> k;
-                k.pr_xpyp = L[Q_PR][q + 1 + G::W];
-                k.pi_xpyp = L[Q_PI][q + 1 + G::W];
-                k.pr_xpzp = Ln[Q_PR][q + 1];
-                k.pi_xpzp = Ln[Q_PI][q + 1];
-                k.pr_ypzp = Ln[Q_PR][q + G::W];
-                k.pi_ypzp = Ln[Q_PI][q + G::W];
-                return k;
-            });
-            if (MODE == MODE_MEASURE && wind)
-                for (int k = 0; k < 3; ++k)
-                    wind[(size_t)k * (size_t)d.N + s] = (int8_t)w3[k];
+        if (MEAS) {
+            // wrap counts: the in-plane links of plane z+1 (this column and
+            // the halo), the z links of plane z at x, x+x and x+y
+            int mx_n, my_n;
+            plane_counts(nb_, nxt.ax, nxt.ay, mx_n, my_n);
+            int mz, mz_xp, mz_yp;
+            const bool s0 = wrap_count_f32(cur.th, nxt.th, (float)cur.az, mz);
+            const bool s1 = wrap_count_f32(lth[cb][q + 1], lth[nb_][q + 1],
+                                           (float)lar[cb][2][q + 1], mz_xp);
+            const bool s2 = wrap_count_f32(lth[cb][q + G::W], lth[nb_][q + G::W],
+                                           (float)lar[cb][2][q + G::W], mz_yp);
+            if (!(s0 && s1 && s2)) {
+                mz = wrap_count(phase64(nxt.pr, nxt.pm) - phase64(pr, pm) + (double)cur.az);
+                mz_xp = wrap_count(phase64(Ln[Q_PR][q + 1], Ln[Q_PI][q + 1]) -
+                                   phase64(pr_xp, pi_xp) + (double)lar[cb][2][q + 1]);
+                mz_yp = wrap_count(phase64(Ln[Q_PR][q + G::W], Ln[Q_PI][q + G::W]) -
+                                   phase64(pr_yp, pi_yp) + (double)lar[cb][2][q + G::W]);
+            }
+            const int my_xp = lcnt[cb][1][q + 1], mx_yp = lcnt[cb][0][q + G::W];
+            if (owner) {
+                // Eqs. (9)-(12) for the site of S_n read above
+                MeasSite<T> mv;
+                mv.pr = pr; mv.pm = pm; mv.pr0 = pr0; mv.pi0 = pi0;
+                mv.ax = cur.ax; mv.ay = cur.ay; mv.az = cur.az;
+                mv.ex0 = ex0; mv.ey0 = ey0; mv.ez0 = ez0;
+                mv.uxc = cur.uxc; mv.uxs = cur.uxs; mv.uyc = cur.uyc; mv.uys = cur.uys;
+                mv.uzc = cur.uzc; mv.uzs = cur.uzs;
+                mv.pr_xp = pr_xp; mv.pi_xp = pi_xp; mv.pr_yp = pr_yp; mv.pi_yp = pi_yp;
+                mv.pr_zp = nxt.pr; mv.pi_zp = nxt.pm;
+                mv.uyc_xp = uyc_xp; mv.uys_xp = uys_xp; mv.uzc_xp = uzc_xp; mv.uzs_xp = uzs_xp;
+                mv.uxc_yp = uxc_yp; mv.uxs_yp = uxs_yp; mv.uzc_yp = uzc_yp; mv.uzs_yp = uzs_yp;
+                mv.uxc_zp = nxt.uxc; mv.uxs_zp = nxt.uxs; mv.uyc_zp = nxt.uyc; mv.uys_zp = nxt.uys;
+                int w3[3] = { 0, 0, 0 };
+                if (measure_densities(macc, mv)) {
+                    // Eq. (11): W_ij = -(m_i(x) + m_j(x+i) - m_i(x+j) - m_j(x))
+                    w3[0] = -(mx_c + my_xp - mx_yp - my_c);
+                    w3[1] = -(my_c + mz_yp - my_n - mz);
+                    w3[2] = -(mz + mx_n - mz_xp - mx_c);
+                    count_windings(macc, w3);
+                }
+            }
+            mx_c = mx_n;
+            my_c = my_n;
         }
 
         phr_m = pr;
@@ -601,21 +646,14 @@ __device__ __forceinline__ void tiled_tile(const RealDesc &d, const Coef &c, int
 }
 
 // One realization: one block per tile, tiles [tile0, tile0 + gridDim.x).
-// The FP32 read-only measuring kernel at 4-row tiles needs 169 VGPRs unhinted (two
-// wavefronts per SIMD); asked for three it fits in 168 with one register spilled and runs
-// 17 % faster (2.78 -> 2.30 ms at 512^3).  The fused measuring step would spill
-// under the same request (3.70 -> 4.33 ms), so it keeps the compiler's choice.
 template <typename T, int TY, int MODE>
 __global__ void __launch_bounds__(64 * TY)
-__attribute__((amdgpu_waves_per_eu(std::is_same<T, float>::value && MODE == MODE_MEASURE &&
-                                           TY == 4 ? 3 : 1)))
-k_step_tiled(const RealDesc *descs, const Coef *coefs, int r, int cz, Slot *slot, int8_t *wind,
-             int tile0) {
+k_step_tiled(const RealDesc *descs, const Coef *coefs, int r, int cz, Slot *slot, int tile0) {
     const RealDesc d = descs[r];
     const Coef c = coefs[r];
-    if (MODE != MODE_MEASURE && !c.active)
+    if (!c.active)
         return;
-    tiled_tile<T, TY, MODE>(d, c, tile0 + xcd_remap(blockIdx.x, gridDim.x), cz, slot, wind);
+    tiled_tile<T, TY, MODE>(d, c, tile0 + xcd_remap(blockIdx.x, gridDim.x), cz, slot);
 }
 
 // Many realizations in one launch: a persistent grid walks the item list in
@@ -639,7 +677,7 @@ k_step_batch(const RealDesc *descs, const Coef *coefs, const BatchItem *items, i
             continue;
         const RealDesc d = descs[item.r];
         tiled_tile<T, TY, MODE>(d, c, item.tile, item.cz,
-                                MODE == MODE_STEP ? nullptr : slots + item.r, nullptr);
+                                MODE == MODE_STEP ? nullptr : slots + item.r);
     }
 }
 

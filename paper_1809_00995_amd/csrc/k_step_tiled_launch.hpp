@@ -4,6 +4,7 @@
 // in the translation unit that includes it, so only the C ABI's unit does.
 #pragma once
 
+#include "k_measure_tiled.hpp"
 #include "k_step_tiled.hpp"
 
 namespace ah {
@@ -26,16 +27,16 @@ inline void tiled_defaults(bool fp64, int nx, int ny, int nz, int &ty, int &cz) 
 
 template <typename T, int TY, int MODE>
 hipError_t launch_tiled_ty(const RealDesc *desc, const Coef *coef, int r, int nx, int ny, int nz,
-                           int cz, Slot *slot, int8_t *wind, hipStream_t stream) {
+                           int cz, Slot *slot, hipStream_t stream) {
     const long blocks = (long)(nx / 64) * ((ny + TY - 1) / TY) * ((nz + cz - 1) / cz);
     hipLaunchKernelGGL((k_step_tiled<T, TY, MODE>), dim3((unsigned)blocks), dim3(64 * TY), 0,
-                       stream, desc, coef, r, cz, slot, wind, 0);
+                       stream, desc, coef, r, cz, slot, 0);
     return hipGetLastError();
 }
 
 template <typename T, int MODE>
 hipError_t launch_tiled_mode(int ty, const RealDesc *desc, const Coef *coef, int r, int nx, int ny,
-                             int nz, int cz, Slot *slot, int8_t *wind, hipStream_t stream) {
+                             int nz, int cz, Slot *slot, hipStream_t stream) {
     // The measuring modes hold ~220 VGPRs: keep them at tiles that do not
     // spill (FP32 <= 8 rows, FP64 <= 4).  The update is the same arithmetic
     // for every tile height, so this only changes the order of the sums.
@@ -44,14 +45,14 @@ hipError_t launch_tiled_mode(int ty, const RealDesc *desc, const Coef *coef, int
     if (ty > TYMAX)
         ty = TYMAX;
     switch (ty) {
-    case 2: return launch_tiled_ty<T, 2, MODE>(desc, coef, r, nx, ny, nz, cz, slot, wind, stream);
-    case 4: return launch_tiled_ty<T, 4, MODE>(desc, coef, r, nx, ny, nz, cz, slot, wind, stream);
+    case 2: return launch_tiled_ty<T, 2, MODE>(desc, coef, r, nx, ny, nz, cz, slot, stream);
+    case 4: return launch_tiled_ty<T, 4, MODE>(desc, coef, r, nx, ny, nz, cz, slot, stream);
     default:
         if constexpr (TYMAX >= 16)
             if (ty == 16)
-                return launch_tiled_ty<T, 16, MODE>(desc, coef, r, nx, ny, nz, cz, slot, wind, stream);
+                return launch_tiled_ty<T, 16, MODE>(desc, coef, r, nx, ny, nz, cz, slot, stream);
         if constexpr (TYMAX >= 8)
-            return launch_tiled_ty<T, 8, MODE>(desc, coef, r, nx, ny, nz, cz, slot, wind, stream);
+            return launch_tiled_ty<T, 8, MODE>(desc, coef, r, nx, ny, nz, cz, slot, stream);
         return hipErrorInvalidValue;
     }
 }
@@ -61,28 +62,53 @@ inline bool tiled_ty_valid(bool fp64, int ty) {
     return ty == 2 || ty == 4 || ty == 8 || (!fp64 && ty == 16);
 }
 
-// Launch one tiled kernel (mode MODE_*) for realization r.
+// Launch one tiled kernel (MODE_STEP or MODE_STEP_MEASURE) for realization r.
 inline int launch_step_tiled(bool fp64, int mode, const RealDesc *desc, const Coef *coef, int r,
                              int nx, int ny, int nz, int tile_y, int chunk_z, Slot *slot,
-                             int8_t *wind, hipStream_t stream) {
+                             hipStream_t stream) {
     int ty = tile_y, cz = chunk_z;
-    // the measuring modes hold ~240 VGPRs (two waves per SIMD): 4-row tiles
-    // (two blocks per CU) are their default
+    // the measuring mode holds ~160-230 VGPRs: 4-row tiles (two or three blocks
+    // per CU) are its default
     if (ty <= 0 && mode != MODE_STEP)
         ty = 4;
     tiled_defaults(fp64, nx, ny, nz, ty, cz);
     if (nx % 64 != 0 || !tiled_ty_valid(fp64, ty) || cz < 1)
         return (int)hipErrorInvalidValue;
     hipError_t e;
-    if (fp64) {
-        e = mode == MODE_STEP ? launch_tiled_mode<double, MODE_STEP>(ty, desc, coef, r, nx, ny, nz, cz, slot, wind, stream)
-          : mode == MODE_STEP_MEASURE ? launch_tiled_mode<double, MODE_STEP_MEASURE>(ty, desc, coef, r, nx, ny, nz, cz, slot, wind, stream)
-          : launch_tiled_mode<double, MODE_MEASURE>(ty, desc, coef, r, nx, ny, nz, cz, slot, wind, stream);
-    } else {
-        e = mode == MODE_STEP ? launch_tiled_mode<float, MODE_STEP>(ty, desc, coef, r, nx, ny, nz, cz, slot, wind, stream)
-          : mode == MODE_STEP_MEASURE ? launch_tiled_mode<float, MODE_STEP_MEASURE>(ty, desc, coef, r, nx, ny, nz, cz, slot, wind, stream)
-          : launch_tiled_mode<float, MODE_MEASURE>(ty, desc, coef, r, nx, ny, nz, cz, slot, wind, stream);
-    }
+    if (fp64)
+        e = mode == MODE_STEP ? launch_tiled_mode<double, MODE_STEP>(ty, desc, coef, r, nx, ny, nz, cz, slot, stream)
+                              : launch_tiled_mode<double, MODE_STEP_MEASURE>(ty, desc, coef, r, nx, ny, nz, cz, slot, stream);
+    else
+        e = mode == MODE_STEP ? launch_tiled_mode<float, MODE_STEP>(ty, desc, coef, r, nx, ny, nz, cz, slot, stream)
+                              : launch_tiled_mode<float, MODE_STEP_MEASURE>(ty, desc, coef, r, nx, ny, nz, cz, slot, stream);
+    return (int)e;
+}
+
+template <typename T, int TY>
+hipError_t launch_measure_ty(const RealDesc *desc, const Coef *coef, int r, int nx, int ny, int nz,
+                             int cz, Slot *slot, int8_t *wind, hipStream_t stream) {
+    const long blocks = (long)(nx / 64) * ((ny + TY - 1) / TY) * ((nz + cz - 1) / cz);
+    hipLaunchKernelGGL((k_measure_tiled<T, TY>), dim3((unsigned)blocks), dim3(64 * TY), 0, stream,
+                       desc, coef, r, cz, slot, wind);
+    return hipGetLastError();
+}
+
+// Launch the read-only measuring pass for realization r: tile heights 2, 4
+// (the default) or 8; other values take the default.
+inline int launch_measure_tiled(bool fp64, const RealDesc *desc, const Coef *coef, int r, int nx,
+                                int ny, int nz, int tile_y, int chunk_z, Slot *slot, int8_t *wind,
+                                hipStream_t stream) {
+    int ty = (tile_y == 2 || tile_y == 4 || tile_y == 8) ? tile_y : 4, cz = chunk_z;
+    tiled_defaults(fp64, nx, ny, nz, ty, cz);
+    if (nx % 64 != 0 || cz < 1)
+        return (int)hipErrorInvalidValue;
+    hipError_t e;
+#define AH_MEAS(T)                                                                                  \
+    (ty == 2 ? launch_measure_ty<T, 2>(desc, coef, r, nx, ny, nz, cz, slot, wind, stream)           \
+     : ty == 8 ? launch_measure_ty<T, 8>(desc, coef, r, nx, ny, nz, cz, slot, wind, stream)         \
+               : launch_measure_ty<T, 4>(desc, coef, r, nx, ny, nz, cz, slot, wind, stream))
+    e = fp64 ? AH_MEAS(double) : AH_MEAS(float);
+#undef AH_MEAS
     return (int)e;
 }
 
