@@ -10,13 +10,16 @@
 - 48 x 128^3 + 16 x 64^3 + 4 x 256^3 (bench.py's ensemble): autotuned tiles, one
   persistent launch per pair, 10-step graphs, diagnostics every 20 steps, against
   one launch per realization, bit for bit, past the 64^3 realizations' n_end.
-- 256^3 radiation era, s = 1, to tau = 64 (640 steps, diagnostics every 10):
-  fields after 10 steps against the oracle (FP64: 1e-12; FP32 from the
-  FP32-rounded start: 1e-5 per field group), diagnostics at step 10 against
-  the oracle, and string length, xi and <v^2> at the end for FP32 against
-  FP64 (1e-3), with Gauss's law and the zero net winding held throughout.
+- 256^3 radiation era, s = 1, to tau = 64 (640 steps, diagnostics every 10) in
+  the production path: fields after 10 steps against the oracle (FP64: 1e-12;
+  FP32 from the FP32-rounded start: 1e-5 per field group), and the whole
+  observation series, end state and winding map (FP64) or the end-time string
+  length, xi and <v^2> (FP32, 1e-3) against the oracle's stored run of the
+  same workload, with Gauss's law and the zero net winding held throughout.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -25,7 +28,8 @@ import torch
 pytestmark = pytest.mark.gpu
 
 AH = pytest.importorskip("paper_1809_00995_amd")
-from tests.gpu_util import (fields_np, group_errors, oracle_params)  # noqa: E402
+from tests.gpu_util import (ambiguous_links, fields_np, group_errors,  # noqa: E402
+                            oracle_params, plaquette_touches)
 
 
 def _edge_coords(n, period):
@@ -223,10 +227,31 @@ def test_full_ensemble_in_benchmark_launch_configuration():
         torch.cuda.empty_cache()
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _rel(a, b):
+    return abs(a - b) / abs(b) if b != 0 else abs(a - b)
+
+
 def test_config_256cubed_radiation_run(O):
+    """256^3 radiation era, s = 1, to tau = 64 in the production path (20-plane
+    layout: pairs, FP32 read-only measuring passes, FP64 fused measuring steps),
+    diagnostics every 10 steps, against the oracle's run of the same workload
+    (tests/golden/make_config2_golden.py): the fields after 10 steps (FP64 1e-12;
+    FP32 from the FP32-rounded start 1e-5 per field group); for FP64 every
+    observation of the series, the end state on 256 sampled sites and the winding
+    map plaquette by plaquette (mismatches only where a link argument lies within
+    1e-6 of pi); for FP32 string length, xi_W, xi_L, <v^2>_X and <v^2>_w at the
+    end within 1e-3 of the oracle's run from the FP32-rounded start, with the
+    divergence along the run printed; Gauss's law and zero net winding held."""
     n, steps, every = 256, 640, 10
     print("CASE test=config_256", flush=True)
-    base = dict(dx=0.5, dt=0.1, tau0=0.0, tau_ref=n * 0.5 / 2, era_p=1.0, s=1.0, seed=1)
+    with open(os.path.join(GOLDEN, "config2_256cubed_radiation_s1.json")) as f:
+        gold = json.load(f)
+    wz = np.load(os.path.join(GOLDEN, "config2_256cubed_radiation_s1_wind640.npz"))
+    base = dict(dx=0.5, dt=0.1, tau0=0.0, tau_ref=n * 0.5 / 2, era_p=1.0, s=1.0, seed=1,
+                layout=AH.AH_LAYOUT_20)
     res = {}
     for prec in (AH.AH_FP64, AH.AH_FP32):
         p = AH.Params(n, n, n, precision=prec, **base)
@@ -234,45 +259,79 @@ def test_config_256cubed_radiation_run(O):
             c.step(10)
             f10 = fields_np(c)
             obs = c.step(steps - 10, measure_every=every)
-            (last,) = c.measure()                   # S_640, tau = 64
+            (last,), (wmap,) = c.measure(wind=True)          # S_640, tau = 64
             mx, _ = c.gauss_residual()
-        res[prec] = (p, f10, [o[0] for o in obs] + [last], mx[0])
+            end = c.fields().reshape(10, -1)
+            idx = torch.tensor(gold["runs"]["fp64"]["end"]["sample_sites"], device=end.device)
+            sample = end[:, idx].double().cpu().numpy().T
+            wmap = wmap.cpu().numpy()
+            state = end.view(10, n, n, n).double().cpu().numpy() if prec == AH.AH_FP64 else None
+        res[prec] = (p, f10, [o[0] for o in obs] + [last], mx[0], sample, wmap, state)
+        torch.cuda.empty_cache()
+
+    # fields after 10 steps against the oracle run here
     op = oracle_params(O, res[AH.AH_FP64][0])
     init = O.init_random_phase(op)
-    ref10, oobs = O.run(op, init, 0, 10, measure_every=10)
+    ref10, _ = O.run(op, init, 0, 10)
+    ref10_32, _ = O.run(op, init.astype(np.float32).astype(np.float64), 0, 10)
     e64 = group_errors(res[AH.AH_FP64][1], ref10)
-    init32 = init.astype(np.float32).astype(np.float64)
-    ref10_32, _ = O.run(op, init32, 0, 10)
     e32 = group_errors(res[AH.AH_FP32][1], ref10_32)
     print("  step-10 field errors FP64:", e64, " FP32:", e32, flush=True)
     assert max(e64.values()) < 1e-12
     assert max(e32.values()) < 1e-5
 
-    o64, o32 = res[AH.AH_FP64][2], res[AH.AH_FP32][2]
-    assert [o.step for o in o64] == list(range(10, steps, every)) + [steps]
-    # diagnostics of S_10 (first measurement of the call) against the oracle
-    ref_m = O.measure(op, 10, ref10)
-    g = o64[0]
-    assert g.n_wind == ref_m.n_wind
-    for k in ("energy", "sum_lag"):
-        assert getattr(g, k) == pytest.approx(getattr(ref_m, k), rel=1e-9), k
-    assert np.allclose(g.v2, ref_m.v2, rtol=1e-9)
-    # properties held at every measurement
-    for o in o64 + o32:
+    # FP64: the whole series against the oracle's
+    g64 = {o["step"]: o for o in gold["runs"]["fp64"]["series"]}
+    o64 = res[AH.AH_FP64][2]
+    assert [o.step for o in o64] == list(range(10, steps + 1, every))
+    worst = {}
+    for o in o64:
+        r = g64[o.step]
         assert o.net_wind_dir == [0, 0, 0] and o.nonfinite == 0
-    assert res[AH.AH_FP64][3] < 1e-12
-    # end time: FP32 against FP64
-    a, b = o32[-1], o64[-1]
-    print(f"  end step {b.step}: n_wind fp64 {b.n_wind} fp32 {a.n_wind}; "
-          f"v2_L {b.v2[0]:.6f} {a.v2[0]:.6f}; v2_V {b.v2[1]:.6f} {a.v2[1]:.6f}; "
-          f"xi_L {b.xi_l:.5f} {a.xi_l:.5f}", flush=True)
-    curve = [(x.step, abs(x.length - y.length) / y.length, abs(x.v2[0] - y.v2[0]) / abs(y.v2[0]))
-             for x, y in zip(o32, o64)]
-    print("  FP32-FP64 relative divergence (step, length, v2_L):",
-          [(s_, f"{l:.1e}", f"{v:.1e}") for s_, l, v in curve[::8]], flush=True)
-    assert a.length == pytest.approx(b.length, rel=1e-3)
-    assert a.xi_w == pytest.approx(b.xi_w, rel=1e-3)
+        assert abs(o.n_wind - r["n_wind"]) <= 2, (o.step, o.n_wind, r["n_wind"])
+        for k in ("length", "energy", "sum_lag"):
+            worst[k] = max(worst.get(k, 0.0), _rel(getattr(o, k), r[k]))
+        # the parts of the energy relative to the whole: the oracle forms
+        # 1 - cos(Xi) directly, which carries only ~1e-16 / Xi^2 relative digits
+        # while the plaquettes are small (early times)
+        for k in ("kin", "grad", "elec", "mag", "pot"):
+            worst[k] = max(worst.get(k, 0.0), abs(getattr(o, k) - r[k]) / r["energy"])
+        for k in range(3):
+            worst[f"v2_{k}"] = max(worst.get(f"v2_{k}", 0.0), _rel(o.v2[k], r["v2"][k]))
+    print("  FP64 series, worst relative deviation from the oracle:",
+          {k: f"{v:.1e}" for k, v in worst.items()}, flush=True)
+    for k, v in worst.items():
+        assert v < 1e-8, k
+    # FP64 end state on sampled sites, Gauss's law, and the winding map
+    ref_s = np.array(gold["runs"]["fp64"]["end"]["sample_fields"])
+    es = group_errors(res[AH.AH_FP64][4].T, ref_s.T)
+    print("  FP64 end fields on 256 sampled sites:", es, flush=True)
+    assert max(es.values()) < 1e-9
+    assert res[AH.AH_FP64][3] < 1e-12 and gold["runs"]["fp64"]["end"]["gauss_max"] < 1e-12
+    ref_w = np.zeros((3, n * n * n), dtype=np.int8)
+    ref_w[wz["orientation"].astype(np.int64), wz["site"].astype(np.int64)] = wz["w"]
+    diff = res[AH.AH_FP64][5].reshape(3, -1) != ref_w
+    allowed = plaquette_touches(ambiguous_links(res[AH.AH_FP64][6])).reshape(3, -1)
+    print(f"  FP64 end winding map: {int(np.count_nonzero(ref_w))} pierced plaquettes, "
+          f"{int(diff.sum())} differ (all must touch a link within 1e-6 of pi)", flush=True)
+    assert not (diff & ~allowed).any()
+
+    # FP32 against the oracle from the FP32-rounded start
+    g32 = {o["step"]: o for o in gold["runs"]["fp32_start"]["series"]}
+    o32 = res[AH.AH_FP32][2]
+    curve = [(o.step, _rel(o.length, g32[o.step]["length"]),
+              _rel(o.v2[0], g32[o.step]["v2"][0])) for o in o32]
+    print("  FP32 vs oracle relative divergence (step, length, v2_L):",
+          [(s_, f"{l:.1e}", f"{v:.1e}") for s_, l, v in curve[::8] + curve[-1:]], flush=True)
+    for o in o32:
+        assert o.net_wind_dir == [0, 0, 0] and o.nonfinite == 0
+    a, b = o32[-1], g32[steps]
+    print(f"  end: n_wind oracle {b['n_wind']} fp32 {a.n_wind}; v2 {b['v2']} {a.v2}; "
+          f"xi_L {b['xi_l']:.5f} {a.xi_l:.5f}", flush=True)
+    for k in ("length", "xi_w", "v2_eos"):
+        assert _rel(getattr(a, k), b[k]) < 1e-3, k
     for k in range(3):
-        assert a.v2[k] == pytest.approx(b.v2[k], rel=1e-3), k
-    assert a.v2_eos == pytest.approx(b.v2_eos, rel=1e-3)
-    assert not math.isnan(b.xi_l) and a.xi_l == pytest.approx(b.xi_l, rel=1e-3)
+        assert _rel(a.v2[k], b["v2"][k]) < 1e-3, k
+    assert not math.isnan(b["xi_l"]) and _rel(a.xi_l, b["xi_l"]) < 1e-3
+    print(f"  Gauss residual at the end: FP64 {res[AH.AH_FP64][3]:.1e}, "
+          f"FP32 {res[AH.AH_FP32][3]:.1e}", flush=True)
