@@ -10,6 +10,7 @@ with s = 1 and s = 0, matter era with s = 0, and radiation with a core-growth
 period (s = -1) before the true equations of motion (s = 1).
 
     python -m paper_1809_00995_amd.scaling --n 512 --seeds 5 --out scaling.json
+    python -m paper_1809_00995_amd.scaling --cases radiation_s0,matter_s0 --window2 0.75
 """
 from __future__ import annotations
 
@@ -77,7 +78,10 @@ def fit(obs, frac_start: float = 0.5):
         out["dxi_" + key[3:]] = float(np.polyfit(tau[ok], xi[ok], 1)[0]) if ok.sum() > 2 else math.nan
     out["v2_V"] = float(np.mean([o.v2[1] for o in late]))
     out["v2_L"] = float(np.mean([o.v2[0] for o in late]))
+    out["v2_rho"] = float(np.mean([o.v2[2] for o in late]))
     out["v2_w"] = float(np.mean([o.v2_eos for o in late]))
+    # the spread of the Lagrangian-weighted estimator between measurements
+    out["v2_L_sd"] = float(np.std([o.v2[0] for o in late]))
     return out
 
 
@@ -87,6 +91,10 @@ def main(argv=None):
     ap.add_argument("--seeds", type=int, default=5)
     ap.add_argument("--cases", default=",".join(DEFAULT_CASES))
     ap.add_argument("--measure-every", type=int, default=10)
+    ap.add_argument("--window", type=float, default=0.5,
+                    help="fit and average over tau >= window * tau_end")
+    ap.add_argument("--window2", type=float, default=0.0,
+                    help="also report the fit over tau >= window2 * tau_end")
     ap.add_argument("--out", default=None)
     ap.add_argument("--series", action="store_true", help="also store each run's observation series")
     args = ap.parse_args(argv)
@@ -97,7 +105,10 @@ def main(argv=None):
         for k in range(args.seeds):
             obs = evolve(args.n, era, s, seed=100 + k, measure_every=args.measure_every,
                          core_growth=cg)
-            runs.append(fit(obs))
+            runs.append(fit(obs, args.window))
+            if args.window2:
+                runs[-1].update({f"{k}@{args.window2:g}": v
+                                 for k, v in fit(obs, args.window2).items()})
             if args.series:
                 runs[-1]["series"] = series(obs, args.n)
             print(f"{name} seed {100 + k}: " + ", ".join(f"{a}={b:.4f}" for a, b in runs[-1].items() if a != "series"),
