@@ -57,6 +57,9 @@ struct ah_ctx {
     BatchItem *d_items2 = nullptr;
     int n_items2 = 0, items2_ty = 0, grid2 = 0;
     bool items2_off32 = false, items2_valid = false;
+    BatchItem *d_items_m = nullptr;   // the read-only measuring pass
+    int n_items_m = 0, grid_m = 0;
+    bool items_m_valid = false;
     // graph replay
     hipStream_t gstream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -196,6 +199,7 @@ bool frozen(const ah_ctx *c, int r) {
 void invalidate_plans(ah_ctx *c) {
     c->items_valid = false;
     c->items2_valid = false;
+    c->items_m_valid = false;
     if (c->gexec)
         (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
@@ -430,6 +434,43 @@ int build_items2(ah_ctx *c) {
     return AH_OK;
 }
 
+// Work list of the batched read-only measuring pass: the two-step kernel's
+// z-chunks (the pairs that follow walk them), 4-row tiles, the same order.
+int build_items_m(ah_ctx *c) {
+    if (c->items_m_valid)
+        return AH_OK;
+    const bool fp64 = c->prec == AH_FP64;
+    const int ty = kMeasureBatchTY;
+    std::vector<int> order(c->nreal);
+    for (int r = 0; r < c->nreal; ++r)
+        order[r] = r;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return sites_of(c->p[a]) > sites_of(c->p[b]); });
+    std::vector<BatchItem> items;
+    for (int r : order) {
+        const ah_params &q = c->p[r];
+        int t = ty, z = c->cz2[r] > 0 ? c->cz2[r] : c->cz[r];
+        tiled_defaults(fp64, q.nx, q.ny, q.nz, t, z);
+        const int tiles = (q.nx / 64) * ((q.ny + ty - 1) / ty) * ((q.nz + z - 1) / z);
+        for (int k = 0; k < tiles; ++k)
+            items.push_back(BatchItem{ r, k, z, 0 });
+    }
+    if (c->d_items_m)
+        (void)hipFree(c->d_items_m);
+    c->d_items_m = nullptr;
+    HIP_TRY(c, hipMalloc(&c->d_items_m, items.size() * sizeof(BatchItem)));
+    HIP_TRY(c, hipMemcpyAsync(c->d_items_m, items.data(), items.size() * sizeof(BatchItem),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int rc = measure_batch_dispatch(fp64, nullptr, nullptr, nullptr, 0, nullptr, 0, nullptr,
+                                    &c->grid_m);
+    if (rc)
+        return fail(c, AH_E_HIP, "occupancy query failed: %s", hipGetErrorString((hipError_t)rc));
+    c->n_items_m = (int)items.size();
+    c->items_m_valid = true;
+    return AH_OK;
+}
+
 // One pass over memory of every realization: bookkeeping for `steps` (1 or
 // 2) steps, then the kernels: the batched kernel of that many steps, or one
 // launch per realization.  slots_row[r] receives the measurement of
@@ -569,7 +610,7 @@ void release(ah_ctx *c) {
     if (c->gstream)
         (void)hipStreamDestroy(c->gstream);
     void *ptrs[] = { c->d_desc, c->d_step, c->d_copy, c->d_coef, c->d_slots, c->d_obs, c->d_gauss,
-                     c->d_items, c->d_items2 };
+                     c->d_items, c->d_items2, c->d_items_m };
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -808,11 +849,12 @@ int ah_step(ah_ctx *c, int64_t nsteps, int32_t measure_every, ah_obs *out, int64
     }
 
     // FP32 with pairs: a measured state whose next stop is an even number of
-    // steps away is measured by a read-only pass and then stepped in pairs
-    // (at 512^3: 2.8 + 2.7 ms against 3.7 + 2.1 ms for the fused measuring step
-    // and the odd single step that would follow); FP64 pairs cost more than
-    // that saves, and slabs and batched launches keep the fused step.
-    const bool ro_measure = two && c->prec == AH_FP32 && c->zh == 0 && !batch_ok(c);
+    // steps away is measured by a read-only pass (one persistent launch in the
+    // batched form) and then stepped in pairs (at 512^3: 2.0 + 2.7 ms against
+    // 3.7 + 2.1 ms for the fused measuring step and the odd single step that
+    // would follow); FP64 pairs cost more than that saves, and slabs keep the
+    // fused step.
+    const bool ro_measure = two && c->prec == AH_FP32 && c->zh == 0;
     size_t next = 0;
     int64_t i = 0;
     while (i < nsteps) {
@@ -820,9 +862,20 @@ int ah_step(ah_ctx *c, int64_t nsteps, int32_t measure_every, ah_obs *out, int64
             const int64_t stop = next + 1 < meas.size() ? meas_at[next + 1] : nsteps;
             if (ro_measure && (stop - i) % 2 == 0) {
                 TRY(launch_bookkeep(c, 0));
-                for (int r = 0; r < c->nreal; ++r)
-                    if (meas[next][r])
-                        TRY(launch_measure(c, r, c->d_slots + next * c->nreal + r, nullptr));
+                if (batch_ok(c)) {
+                    // frozen realizations (past their n_end) are skipped on the device
+                    TRY(build_items_m(c));
+                    int rc = measure_batch_dispatch(false, c->d_desc, c->d_coef, c->d_items_m,
+                                                    c->n_items_m, c->d_slots + next * c->nreal,
+                                                    c->grid_m, c->stream, nullptr);
+                    if (rc)
+                        return fail(c, AH_E_HIP, "batched measuring kernel launch failed: %s",
+                                    hipGetErrorString((hipError_t)rc));
+                } else {
+                    for (int r = 0; r < c->nreal; ++r)
+                        if (meas[next][r])
+                            TRY(launch_measure(c, r, c->d_slots + next * c->nreal + r, nullptr));
+                }
                 ++next;
                 continue;   // the steps from i go in pairs
             }

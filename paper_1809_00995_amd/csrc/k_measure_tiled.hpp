@@ -259,4 +259,27 @@ k_measure_tiled(const RealDesc *descs, const Coef *coefs, int r, int cz, Slot *s
     measure_tile<T, TY>(d, c, xcd_remap(blockIdx.x, gridDim.x), cz, slot, wind);
 }
 
+// Many realizations in one launch (the ensemble form): a persistent grid walks
+// the item list (realization, tile, z-chunk) in rounds of gridDim.x items, as
+// the batched step kernels do; a realization whose state is past its n_end is
+// skipped, and every other one measures into slots[r].
+template <typename T, int TY>
+__global__ void __launch_bounds__(64 * TY)
+k_measure_batch(const RealDesc *descs, const Coef *coefs, const BatchItem *items, int n_items,
+                Slot *slots) {
+    const int g = gridDim.x;
+    const int b = xcd_remap(blockIdx.x, g);
+    for (int base = 0; base < n_items; base += g) {
+        const int it = base + b;
+        if (it >= n_items)
+            break;
+        const BatchItem item = items[it];
+        const Coef c = coefs[item.r];
+        if (!c.active)
+            continue;
+        const RealDesc d = descs[item.r];
+        measure_tile<T, TY>(d, c, item.tile, item.cz, slots + item.r, nullptr);
+    }
+}
+
 } // namespace ah

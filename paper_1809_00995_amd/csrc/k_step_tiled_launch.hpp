@@ -112,6 +112,43 @@ inline int launch_measure_tiled(bool fp64, const RealDesc *desc, const Coef *coe
     return (int)e;
 }
 
+// Tile height of the batched read-only measuring pass.
+constexpr int kMeasureBatchTY = 4;
+
+// The batched read-only measuring pass: with grid_out != NULL only the
+// resident-block count (occupancy x compute units) is returned; otherwise the
+// kernel is launched on `grid` blocks over the n_items items.
+inline int measure_batch_dispatch(bool fp64, const RealDesc *desc, const Coef *coef,
+                                  const BatchItem *items, int n_items, Slot *slots, int grid,
+                                  hipStream_t stream, int *grid_out) {
+    constexpr int TY = kMeasureBatchTY;
+    hipError_t e;
+    if (grid_out) {
+        int per_cu = 0, dev = 0, cus = 0;
+        e = hipGetDevice(&dev);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_measure_batch<double, TY>,
+                                                                   64 * TY, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_measure_batch<float, TY>,
+                                                                   64 * TY, 0);
+        *grid_out = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+        return (int)e;
+    }
+    if (grid > n_items)
+        grid = n_items;
+    if (grid < 1)
+        return (int)hipSuccess;
+    if (fp64)
+        hipLaunchKernelGGL((k_measure_batch<double, TY>), dim3((unsigned)grid), dim3(64 * TY), 0,
+                           stream, desc, coef, items, n_items, slots);
+    else
+        hipLaunchKernelGGL((k_measure_batch<float, TY>), dim3((unsigned)grid), dim3(64 * TY), 0,
+                           stream, desc, coef, items, n_items, slots);
+    return (int)hipGetLastError();
+}
+
 // Largest tile height of a mode (the measuring modes hold ~220 VGPRs).
 inline int tiled_ty_max(bool fp64, int mode) {
     return mode != MODE_STEP ? (fp64 ? 4 : 8) : (fp64 ? 8 : 16);
