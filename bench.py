@@ -12,7 +12,9 @@ Prints ONE JSON line: FP32 storage and arithmetic (FP64 bookkeeping and
 reductions) is the headline ``value``, in the 20-plane layout where unmeasured
 steps go in pairs through the two-steps-per-pass kernel (``--layout 15``: one
 step per pass).  The other layout, the FP64 kernels and the plain FP64 kernel
-are reported beside it.  ``roofline`` is for the dominant kernel (the step
+are reported beside it.  A plain device-to-device copy runs first: its rate is the
+reference bandwidth of the line, and its half second of work brings the GPU to its working
+clock before any form is timed.  ``roofline`` is for the dominant kernel (the step
 kernel): its mean launch time is taken inside the timed region, from HIP events
 on the library's stream around the passes that measured nothing (one launch of
 it each, after a few-microsecond bookkeeping kernel); ``cpu_baseline`` times the
@@ -56,8 +58,9 @@ def parse():
 
 
 def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15, s=0.0):
-    """Time `steps` steps with the measurement cadence after `warmup` steps,
-    then the same number of steps without diagnostics.  Both timed regions are
+    """Time `steps` steps with the measurement cadence after `warmup` steps (one more,
+    untimed, when that leaves an odd step index and passes go in pairs), then the same
+    number of steps without diagnostics.  Both timed regions are
     one library call per pass (one step, or a pair with the two-step kernel),
     each bracketed by events on the library's stream, so the dominant kernel's
     duration is read inside the timed region from the calls that measured
@@ -76,6 +79,12 @@ def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15, s=0.0):
         ctx.set_kernel(kernel)
     stream = ctx.stream
     ctx.step(warmup)
+    # with pairs, the timed region starts on an even step (one more untimed step when
+    # the warmup count is odd), so that it takes the same passes as the steady state
+    # of a long run: pairs, and at each measured state the read-only pass
+    extra = ctx.current_step() % per
+    if extra:
+        ctx.step(extra)
     torch.cuda.synchronize()
 
     def ev():
@@ -115,6 +124,7 @@ def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15, s=0.0):
     del planes
     torch.cuda.empty_cache()
     return {"rate": n ** 3 * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+            "warmup_steps": warmup + extra,
             "rate_no_diag": n ** 3 * steps / (ms_nd * 1e-3), "kernel_ms": sum(kt) / len(kt),
             "kernel_ms_median": kt[len(kt) // 2], "launches_timed": len(kt), "per": per,
             "last": last}
@@ -271,6 +281,26 @@ def run_ensemble(AH, torch, batched, graph_steps, tune, layout=20):
     return total / sec, sec, tuning
 
 
+def device_copy_rate(torch, reps=200, timed=20):
+    """GB/s (read + write) of a plain 1 GiB device-to-device copy on this GPU, the mean of
+    the last `timed` of `reps` copies.  Run before the first timed form, the copies also
+    bring the GPU to its working clock (about half a second of full-bandwidth work)."""
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps - timed):
+        dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(timed):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    rate = timed * 2 * src.numel() * 4 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return rate
+
+
 def oracle_rate(n, k):
     """Site-updates/s of the FP64 oracle (test infrastructure) over k steps of an n^3
     matter-era lattice, and the seconds it took."""
@@ -334,6 +364,7 @@ def main():
     n, K, W = args.n, args.steps, args.warmup
     other = 15 if args.layout == 20 else 20
 
+    copy_gbs = device_copy_rate(torch)
     f32 = run_form(AH, torch, n, AH.AH_FP32, kern, K, W, args.layout)
     rate32, ms32, kms32, per32, last32 = (f32["rate"], f32["ms_per_step"], f32["kernel_ms"],
                                           f32["per"], f32["last"])
@@ -351,6 +382,7 @@ def main():
         "value": rate32, "unit": "site-updates/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": ms32, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
+        "warmup_steps_run": f32["warmup_steps"],
         "config": {"workload": f"{n}^3 periodic lattice, matter era a~tau^2, s=0, lambda0=2, "
                                f"e0=1, sigma=1, dx=0.5, dt=0.1, random-phase init, string "
                                f"length and <v^2> every {MEASURE_EVERY} steps",
@@ -442,19 +474,6 @@ def main():
             "per_realization_launches": {"value": rs, "seconds": ss},
             "speedup_vs_per_realization": rb / rs,
             "one_step_per_pass": {"value": r15, "seconds": s15, "layout": 15}}
-    # reference: a plain 1 GiB device-to-device copy on this GPU (read + write)
-    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    c0.record()
-    for _ in range(5):
-        dst.copy_(src)
-    c1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 5 * 2 * src.numel() * 4 / (c0.elapsed_time(c1) * 1e-3) / 1e9
-    del src, dst
-    torch.cuda.empty_cache()
     line["roofline"]["copy_GBs"] = copy_gbs
     if traffic is not None:
         line["roofline"]["traffic_frac_of_copy"] = line["roofline"]["traffic_GBs"] / copy_gbs
