@@ -59,7 +59,7 @@ struct ah_ctx {
     bool items2_off32 = false, items2_valid = false;
     BatchItem *d_items_m = nullptr;   // the read-only measuring pass
     int n_items_m = 0, grid_m = 0;
-    bool items_m_valid = false;
+    bool items_m_valid = false, items_m_off32 = false;
     // graph replay
     hipStream_t gstream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -324,7 +324,7 @@ int launch_measure(ah_ctx *c, int r, Slot *slot, int8_t *wind) {
         return launch_measure_plain(c, r, slot, wind);
     const ah_params &q = c->p[r];
     int rc = launch_measure_tiled(c->prec == AH_FP64, c->d_desc, c->d_coef, r, q.nx, q.ny, q.nz,
-                                  c->tile_y, c->cz[r], slot, wind, c->stream);
+                                  sites_of(q), c->tile_y, c->cz[r], slot, wind, c->stream);
     if (rc)
         return fail(c, AH_E_HIP, "measuring kernel launch failed: %s",
                     hipGetErrorString((hipError_t)rc));
@@ -462,11 +462,15 @@ int build_items_m(ah_ctx *c) {
     HIP_TRY(c, hipMemcpyAsync(c->d_items_m, items.data(), items.size() * sizeof(BatchItem),
                               hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    int rc = measure_batch_dispatch(fp64, nullptr, nullptr, nullptr, 0, nullptr, 0, nullptr,
+    bool off32 = true;
+    for (const auto &q : c->p)
+        off32 = off32 && fits_off32(sites_of(q), fp64 ? 8 : 4);
+    int rc = measure_batch_dispatch(fp64, off32, nullptr, nullptr, nullptr, 0, nullptr, 0, nullptr,
                                     &c->grid_m);
     if (rc)
         return fail(c, AH_E_HIP, "occupancy query failed: %s", hipGetErrorString((hipError_t)rc));
     c->n_items_m = (int)items.size();
+    c->items_m_off32 = off32;
     c->items_m_valid = true;
     return AH_OK;
 }
@@ -865,7 +869,7 @@ int ah_step(ah_ctx *c, int64_t nsteps, int32_t measure_every, ah_obs *out, int64
                 if (batch_ok(c)) {
                     // frozen realizations (past their n_end) are skipped on the device
                     TRY(build_items_m(c));
-                    int rc = measure_batch_dispatch(false, c->d_desc, c->d_coef, c->d_items_m,
+                    int rc = measure_batch_dispatch(false, c->items_m_off32, c->d_desc, c->d_coef, c->d_items_m,
                                                     c->n_items_m, c->d_slots + next * c->nreal,
                                                     c->grid_m, c->stream, nullptr);
                     if (rc)
@@ -974,8 +978,8 @@ int ah_measure_noalloc(int32_t n_real, const ah_params *p, const ah_buffers *buf
         const ah_params &q = p[r];
         int8_t *w = wind_dev ? wind_dev + off : nullptr;
         if (q.nx % 64 == 0) {
-            int rc = launch_measure_tiled(fp64, descs, coefs, r, q.nx, q.ny, q.nz, 0, 0, slots + r,
-                                          w, st);
+            int rc = launch_measure_tiled(fp64, descs, coefs, r, q.nx, q.ny, q.nz, sites_of(q), 0, 0,
+                                          slots + r, w, st);
             if (rc)
                 return fail(nullptr, AH_E_HIP, "tiled measuring kernel launch failed: %s",
                             hipGetErrorString((hipError_t)rc));

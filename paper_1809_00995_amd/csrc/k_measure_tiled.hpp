@@ -19,13 +19,15 @@
 //    staged the site; the halo sites' by the halo threads) and of plane z's
 //    z links at x, x+x and x+y, then measures plane z, then stages plane z+2
 //    into plane z's buffer.
+//  - OFF32: every plane is below 4 GiB, so each global address is one 32-bit
+//    byte offset from a plane base held in scalar registers.
 #pragma once
 
 #include "k_step_tiled.hpp"
 
 namespace ah {
 
-template <typename T, int TY>
+template <typename T, int TY, bool OFF32>
 __device__ __forceinline__ void measure_tile(const RealDesc &d, const Coef &c, int tile, int cz,
                                              Slot *slot, int8_t *wind) {
     using G = TileGeom<TY>;
@@ -77,22 +79,29 @@ __device__ __forceinline__ void measure_tile(const RealDesc &d, const Coef &c, i
     struct Mom {
         T pr, pi, ex, ey, ez;
     };
+    // element s of a plane
+    auto at = [&](gptr<const T> base, int s) -> gptr<const T> {
+        if constexpr (OFF32)
+            return (gptr<const T>)((gptr<const char>)base + (uint32_t)s * (uint32_t)sizeof(T));
+        else
+            return base + s;
+    };
     auto fetch = [&](int z, int xy, Raw &w) {
         const int s = xy + plane_sites * zmap(d, z);
-        w.pr = phr[s];
-        w.pm = phi[s];
-        w.ax = A0[s];
-        w.ay = A1[s];
-        w.az = A2[s];
+        w.pr = *at(phr, s);
+        w.pm = *at(phi, s);
+        w.ax = *at(A0, s);
+        w.ay = *at(A1, s);
+        w.az = *at(A2, s);
     };
     auto fetch_mom = [&](int z, Mom &m) {
         // read once, by this thread only: streaming loads
         const int s = own_xy + plane_sites * zmap(d, z);
-        m.pr = __builtin_nontemporal_load(pir + s);
-        m.pi = __builtin_nontemporal_load(pii + s);
-        m.ex = __builtin_nontemporal_load(E0 + s);
-        m.ey = __builtin_nontemporal_load(E1 + s);
-        m.ez = __builtin_nontemporal_load(E2 + s);
+        m.pr = __builtin_nontemporal_load(at(pir, s));
+        m.pi = __builtin_nontemporal_load(at(pii, s));
+        m.ex = __builtin_nontemporal_load(at(E0, s));
+        m.ey = __builtin_nontemporal_load(at(E1, s));
+        m.ez = __builtin_nontemporal_load(at(E2, s));
     };
     // phasors and phase of a site into LDS buffer bf at k
     auto stage = [&](int bf, int k, const Raw &w, SiteV<T> &v) {
@@ -250,21 +259,24 @@ __device__ __forceinline__ void measure_tile(const RealDesc &d, const Coef &c, i
 
 // One realization: one block per tile and z-chunk (tiles numbered x-fastest,
 // then y, then z-chunk), with the XCD remap of the step kernels.
-template <typename T, int TY>
+template <typename T, int TY, bool OFF32>
 __global__ void __launch_bounds__(64 * TY)
 k_measure_tiled(const RealDesc *descs, const Coef *coefs, int r, int cz, Slot *slot,
                 int8_t *wind) {
     const RealDesc d = descs[r];
     const Coef c = coefs[r];
-    measure_tile<T, TY>(d, c, xcd_remap(blockIdx.x, gridDim.x), cz, slot, wind);
+    measure_tile<T, TY, OFF32>(d, c, xcd_remap(blockIdx.x, gridDim.x), cz, slot, wind);
 }
 
 // Many realizations in one launch (the ensemble form): a persistent grid walks
 // the item list (realization, tile, z-chunk) in rounds of gridDim.x items, as
 // the batched step kernels do; a realization whose state is past its n_end is
-// skipped, and every other one measures into slots[r].
-template <typename T, int TY>
-__global__ void __launch_bounds__(64 * TY)
+// skipped, and every other one measures into slots[r].  OFF32: every
+// realization's planes are below 4 GiB.  The FP32 form is held to three
+// wavefronts per SIMD (at most 168 VGPRs), the occupancy of the single-
+// realization pass; the item loop alone would take it one register past.
+template <typename T, int TY, bool OFF32>
+__global__ void __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
 k_measure_batch(const RealDesc *descs, const Coef *coefs, const BatchItem *items, int n_items,
                 Slot *slots) {
     const int g = gridDim.x;
@@ -278,7 +290,7 @@ k_measure_batch(const RealDesc *descs, const Coef *coefs, const BatchItem *items
         if (!c.active)
             continue;
         const RealDesc d = descs[item.r];
-        measure_tile<T, TY>(d, c, item.tile, item.cz, slots + item.r, nullptr);
+        measure_tile<T, TY, OFF32>(d, c, item.tile, item.cz, slots + item.r, nullptr);
     }
 }
 

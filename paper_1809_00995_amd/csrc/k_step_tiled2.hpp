@@ -39,17 +39,18 @@
 
 namespace ah {
 
-template <int TY> struct Tile2Geom {
-    static constexpr int W1 = 66, H1 = TY + 2, S1 = W1 * H1;   // R1
-    static constexpr int W2 = 68, H2 = TY + 4, S2 = W2 * H2;   // R2
+// R1 and R2 are W x H sites; their LDS rows are P = W + PAD elements apart.
+template <int TY, int PAD = 0> struct Tile2Geom {
+    static constexpr int W1 = 66, H1 = TY + 2, P1 = W1 + PAD, S1 = P1 * H1;   // R1
+    static constexpr int W2 = 68, H2 = TY + 4, P2 = W2 + PAD, S2 = P2 * H2;   // R2
     static constexpr int RING1 = 2 * W1 + 2 * TY;              // R1 minus the tile
     static constexpr int RING2 = 2 * W2 + 2 * H1;              // R2 minus R1
     static constexpr int NRW = (RING1 + 63) / 64;              // ring wavefronts
     static constexpr int NW = TY + NRW;                        // wavefronts per block
     static_assert(RING2 <= 64 * NRW, "the ring wavefronts stage the outer ring");
     static_assert(NW <= 16, "at most 1024 threads per block");
-    static __device__ __forceinline__ int i1(int lx, int ly) { return (ly + 1) * W1 + (lx + 1); }
-    static __device__ __forceinline__ int i2(int lx, int ly) { return (ly + 2) * W2 + (lx + 2); }
+    static __device__ __forceinline__ int i1(int lx, int ly) { return (ly + 1) * P1 + (lx + 1); }
+    static __device__ __forceinline__ int i2(int lx, int ly) { return (ly + 2) * P2 + (lx + 2); }
     // h-th site of the R1 ring: rows -1 and TY (x = -1..64), then columns -1 and 64 (y = 0..TY-1)
     static __device__ __forceinline__ void ring1(int h, int &lx, int &ly) {
         if (h < W1) {
@@ -83,6 +84,13 @@ template <int TY> struct Tile2Geom {
         }
     }
 };
+
+// LDS row padding of the two-step kernel by element type.  FP32 rows take one
+// element more: with odd pitches the ring wavefronts' column accesses (lanes one
+// row apart) fall in distinct banks.  FP64 has no LDS to spare (159.4 KiB of the
+// 160 KiB at TY = 5).
+template <typename T> inline constexpr int kTile2Pad = 0;
+template <> inline constexpr int kTile2Pad<float> = 1;
 
 // phi and the three link phasors of one site (the LDS record of a state).
 template <typename T> struct Phasors {
@@ -210,7 +218,7 @@ __device__ __forceinline__ Phasors<T> make_phasors(T pr, T pm, T ax, T ay, T az)
 template <typename T, int TY, bool OFF32>
 __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, const Coef &c1,
                                             int tile, int cz) {
-    using G = Tile2Geom<TY>;
+    using G = Tile2Geom<TY, kTile2Pad<T>>;
     __shared__ T sa[2][Q_COUNT][G::S2];   // S_n on R2, planes z and z+1
     __shared__ T sb[2][Q_COUNT][G::S1];   // S_{n+1} on R1, two planes
     __shared__ T pa[3][G::S2];            // forward plaquettes of S_n, plane of step one
@@ -318,7 +326,7 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
         lds_barrier();
         bel.pyz = bel.pzx = 0;
         if (has1)
-            base_plaquettes<T, G::W2, G::S2>(sa[1], q2, pbel, pcur, bel.pyz, bel.pzx);
+            base_plaquettes<T, G::P2, G::S2>(sa[1], q2, pbel, pcur, bel.pyz, bel.pzx);
         bel.pr = pbel.pr;
         bel.pm = pbel.pm;
         bel.uzc = pbel.uzc;
@@ -394,7 +402,7 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
         if (has1) {
             nxt.p = make_phasors(nxt.r.pr, nxt.r.pm, nxt.r.ax, nxt.r.ay, nxt.r.az);
             put_phasors<T, G::S2>(sa[NB], q2, nxt.p);
-            fp = fwd_plaquettes<T, G::W2, G::S2>(sa[CB], q2, cur.p, nxt.p);
+            fp = fwd_plaquettes<T, G::P2, G::S2>(sa[CB], q2, cur.p, nxt.p);
             pa[0][q2] = fp.xy;
             pa[1][q2] = fp.yz;
             pa[2][q2] = fp.zx;
@@ -404,7 +412,7 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
             put_phasors<T, G::S2>(sa[NB], rq, up);
             if (edge2) {
                 const Plaq3<T> rp =
-                    fwd_plaquettes<T, G::W2, G::S2>(sa[CB], rq, get_phasors<T, G::S2>(sa[CB], rq), up);
+                    fwd_plaquettes<T, G::P2, G::S2>(sa[CB], rq, get_phasors<T, G::S2>(sa[CB], rq), up);
                 pa[0][rq] = rp.xy;
                 pa[1][rq] = rp.yz;
                 pa[2][rq] = rp.zx;
@@ -418,7 +426,7 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
         // S_{n+1} at zs-1, which need the own site's S_{n+1} at zs just formed
         Plaq3<T> fp1{};
         if (has1) {
-            const Stencil<T> st = gather<T, G::W2, G::S2>(sa[CB], pa, q2, cur.p, cur.r.ax,
+            const Stencil<T> st = gather<T, G::P2, G::S2>(sa[CB], pa, q2, cur.p, cur.r.ax,
                                                           cur.r.ay, cur.r.az, nxt.p, bel, pr0,
                                                           pi0, ex0, ey0, ez0, fp);
             n1.v = leapfrog_site(st, K0);
@@ -432,7 +440,7 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
                 n1.p = make_phasors(n1.v.qr, n1.v.qi, n1.v.ax, n1.v.ay, n1.v.az);
                 put_phasors<T, G::S1>(sb[CB], q1, n1.p);
                 if (need1 && k >= 1) {
-                    fp1 = fwd_plaquettes<T, G::W1, G::S1>(sb[NB], q1, c1.p, n1.p);
+                    fp1 = fwd_plaquettes<T, G::P1, G::S1>(sb[NB], q1, c1.p, n1.p);
                     pb[0][q1] = fp1.xy;
                     pb[1][q1] = fp1.yz;
                     pb[2][q1] = fp1.zx;
@@ -451,7 +459,7 @@ __device__ __forceinline__ void tiled2_tile(const RealDesc &d, const Coef &c0, c
         // (c) step two at (tile site, zs - 1), one plane behind
         if (inner) {
             if (k >= 2) {
-                const Stencil<T> st = gather<T, G::W1, G::S1>(sb[NB], pb, q1, c1.p, c1.v.ax,
+                const Stencil<T> st = gather<T, G::P1, G::S1>(sb[NB], pb, q1, c1.p, c1.v.ax,
                                                               c1.v.ay, c1.v.az, n1.p, bel1,
                                                               c1.v.pr, c1.v.pi, c1.v.ex,
                                                               c1.v.ey, c1.v.ez, fp1);

@@ -6,6 +6,7 @@
 
 #include "k_measure_tiled.hpp"
 #include "k_step_tiled.hpp"
+#include "k_step_tiled2_api.hpp"
 
 namespace ah {
 
@@ -86,27 +87,34 @@ inline int launch_step_tiled(bool fp64, int mode, const RealDesc *desc, const Co
 
 template <typename T, int TY>
 hipError_t launch_measure_ty(const RealDesc *desc, const Coef *coef, int r, int nx, int ny, int nz,
-                             int cz, Slot *slot, int8_t *wind, hipStream_t stream) {
+                             int cz, bool off32, Slot *slot, int8_t *wind, hipStream_t stream) {
     const long blocks = (long)(nx / 64) * ((ny + TY - 1) / TY) * ((nz + cz - 1) / cz);
-    hipLaunchKernelGGL((k_measure_tiled<T, TY>), dim3((unsigned)blocks), dim3(64 * TY), 0, stream,
-                       desc, coef, r, cz, slot, wind);
+    if (off32)
+        hipLaunchKernelGGL((k_measure_tiled<T, TY, true>), dim3((unsigned)blocks), dim3(64 * TY), 0,
+                           stream, desc, coef, r, cz, slot, wind);
+    else
+        hipLaunchKernelGGL((k_measure_tiled<T, TY, false>), dim3((unsigned)blocks), dim3(64 * TY), 0,
+                           stream, desc, coef, r, cz, slot, wind);
     return hipGetLastError();
 }
 
 // Launch the read-only measuring pass for realization r: tile heights 2, 4
-// (the default) or 8; other values take the default.
+// (the default) or 8; other values take the default.  stored_sites: the
+// elements of one field plane (nx ny (nz + 2 z_halo)), which decides the
+// address form.
 inline int launch_measure_tiled(bool fp64, const RealDesc *desc, const Coef *coef, int r, int nx,
-                                int ny, int nz, int tile_y, int chunk_z, Slot *slot, int8_t *wind,
-                                hipStream_t stream) {
+                                int ny, int nz, long stored_sites, int tile_y, int chunk_z,
+                                Slot *slot, int8_t *wind, hipStream_t stream) {
     int ty = (tile_y == 2 || tile_y == 4 || tile_y == 8) ? tile_y : 4, cz = chunk_z;
     tiled_defaults(fp64, nx, ny, nz, ty, cz);
     if (nx % 64 != 0 || cz < 1)
         return (int)hipErrorInvalidValue;
+    const bool off32 = fits_off32(stored_sites, fp64 ? 8 : 4);
     hipError_t e;
 #define AH_MEAS(T)                                                                                  \
-    (ty == 2 ? launch_measure_ty<T, 2>(desc, coef, r, nx, ny, nz, cz, slot, wind, stream)           \
-     : ty == 8 ? launch_measure_ty<T, 8>(desc, coef, r, nx, ny, nz, cz, slot, wind, stream)         \
-               : launch_measure_ty<T, 4>(desc, coef, r, nx, ny, nz, cz, slot, wind, stream))
+    (ty == 2 ? launch_measure_ty<T, 2>(desc, coef, r, nx, ny, nz, cz, off32, slot, wind, stream)    \
+     : ty == 8 ? launch_measure_ty<T, 8>(desc, coef, r, nx, ny, nz, cz, off32, slot, wind, stream)  \
+               : launch_measure_ty<T, 4>(desc, coef, r, nx, ny, nz, cz, off32, slot, wind, stream))
     e = fp64 ? AH_MEAS(double) : AH_MEAS(float);
 #undef AH_MEAS
     return (int)e;
@@ -115,38 +123,45 @@ inline int launch_measure_tiled(bool fp64, const RealDesc *desc, const Coef *coe
 // Tile height of the batched read-only measuring pass.
 constexpr int kMeasureBatchTY = 4;
 
-// The batched read-only measuring pass: with grid_out != NULL only the
-// resident-block count (occupancy x compute units) is returned; otherwise the
-// kernel is launched on `grid` blocks over the n_items items.
-inline int measure_batch_dispatch(bool fp64, const RealDesc *desc, const Coef *coef,
-                                  const BatchItem *items, int n_items, Slot *slots, int grid,
-                                  hipStream_t stream, int *grid_out) {
+template <typename T, bool OFF32>
+hipError_t measure_batch_t(const RealDesc *desc, const Coef *coef, const BatchItem *items,
+                           int n_items, Slot *slots, int grid, hipStream_t stream, int *grid_out) {
     constexpr int TY = kMeasureBatchTY;
-    hipError_t e;
     if (grid_out) {
         int per_cu = 0, dev = 0, cus = 0;
-        e = hipGetDevice(&dev);
+        hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess)
             e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
-            e = fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_measure_batch<double, TY>,
-                                                                   64 * TY, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_measure_batch<float, TY>,
-                                                                   64 * TY, 0);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_measure_batch<T, TY, OFF32>,
+                                                             64 * TY, 0);
         *grid_out = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
-        return (int)e;
+        return e;
     }
     if (grid > n_items)
         grid = n_items;
     if (grid < 1)
-        return (int)hipSuccess;
+        return hipSuccess;
+    hipLaunchKernelGGL((k_measure_batch<T, TY, OFF32>), dim3((unsigned)grid), dim3(64 * TY), 0,
+                       stream, desc, coef, items, n_items, slots);
+    return hipGetLastError();
+}
+
+// The batched read-only measuring pass: with grid_out != NULL only the
+// resident-block count (occupancy x compute units) is returned; otherwise the
+// kernel is launched on `grid` blocks over the n_items items.  off32: every
+// realization's planes are below 4 GiB.
+inline int measure_batch_dispatch(bool fp64, bool off32, const RealDesc *desc, const Coef *coef,
+                                  const BatchItem *items, int n_items, Slot *slots, int grid,
+                                  hipStream_t stream, int *grid_out) {
+    hipError_t e;
     if (fp64)
-        hipLaunchKernelGGL((k_measure_batch<double, TY>), dim3((unsigned)grid), dim3(64 * TY), 0,
-                           stream, desc, coef, items, n_items, slots);
+        e = off32 ? measure_batch_t<double, true>(desc, coef, items, n_items, slots, grid, stream, grid_out)
+                  : measure_batch_t<double, false>(desc, coef, items, n_items, slots, grid, stream, grid_out);
     else
-        hipLaunchKernelGGL((k_measure_batch<float, TY>), dim3((unsigned)grid), dim3(64 * TY), 0,
-                           stream, desc, coef, items, n_items, slots);
-    return (int)hipGetLastError();
+        e = off32 ? measure_batch_t<float, true>(desc, coef, items, n_items, slots, grid, stream, grid_out)
+                  : measure_batch_t<float, false>(desc, coef, items, n_items, slots, grid, stream, grid_out);
+    return (int)e;
 }
 
 // Largest tile height of a mode (the measuring modes hold ~220 VGPRs).

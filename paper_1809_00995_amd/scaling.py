@@ -6,8 +6,9 @@ and reports, per case, the slopes
 dxi/dtau of the Lagrangian and winding string separations and the mean of
 the velocity estimators over the late, scaling part of the run, averaged
 over seeds with their standard error.  Cases follow Table 3: radiation era
-with s = 1 and s = 0, matter era with s = 0, and radiation with a core-growth
-period (s = -1) before the true equations of motion (s = 1).
+with s = 1 and s = 0, matter era with s = 0, radiation with a core-growth
+period (s = -1) before the true equations of motion (s = 1), and either era
+with fixed comoving width (s = 0) before them.
 
     python -m paper_1809_00995_amd.scaling --n 512 --seeds 5 --out scaling.json
     python -m paper_1809_00995_amd.scaling --cases radiation_s0,matter_s0 --window2 0.75
@@ -29,17 +30,27 @@ from . import ah as AH
 # a(tau_cg) = 1 so that the couplings e0 a^(s-1), lambda0 a^(2(s-1)) are continuous there;
 # the comoving core width (e0 sigma)^-1 a^(-s) then grows as a until tau_cg and shrinks
 # as 1/a after it.  The run starts at tau0 = tau_end / 4, where the width is half its
-# peak, so that it stays within [dx, 2 dx] for dx = 0.5 in radiation (p = 1).
+# peak, so that it stays within [dx, 2 dx] for dx = 0.5 in radiation (p = 1).  With
+# "fixed" s = 0 until tau_s = tau_end / 2 and s afterwards, from tau = 0.
 CASES = {"radiation_s1": (1.0, 1.0, False), "radiation_s0": (1.0, 0.0, False),
-         "matter_s0": (2.0, 0.0, False), "radiation_s1_core_growth": (1.0, 1.0, True)}
+         "matter_s0": (2.0, 0.0, False), "radiation_s1_core_growth": (1.0, 1.0, True),
+         "radiation_s0_then_s1": (1.0, 1.0, "fixed"), "matter_s0_then_s1": (2.0, 1.0, "fixed")}
 DEFAULT_CASES = ("radiation_s0", "matter_s0", "radiation_s1_core_growth")
 
 
 def evolve(n: int, era: float, s: float, seed: int, measure_every: int = 10, dx: float = 0.5,
-           dt: float = 0.1, core_growth: bool = False):
+           dt: float = 0.1, core_growth=False):
     """One run to tau_end = n dx / 2; returns the observation series."""
     tau_end = n * dx / 2.0
-    if core_growth:
+    if core_growth == "fixed":
+        # fixed comoving width (s = 0) until tau_s = tau_end / 2, then the true
+        # equations of motion (s = 1), with a(tau_s) = 1: the width is 1/(e0 sigma)
+        # until tau_s and shrinks as 1/a after it, to 2^-p/(e0 sigma) at tau_end
+        p = AH.Params(n, n, n, precision=AH.AH_FP32, dx=dx, dt=dt, tau0=0.0,
+                      tau_ref=tau_end / 2, era_p=era, s=0.0, s_late=s, tau_s=tau_end / 2,
+                      seed=seed, layout=AH.AH_LAYOUT_20)
+        tau0 = 0.0
+    elif core_growth:
         tau0 = round(0.25 * tau_end / dt) * dt
         p = AH.Params(n, n, n, precision=AH.AH_FP32, dx=dx, dt=dt, tau0=tau0,
                       tau_ref=tau_end / 2, era_p=era, s=-1.0, s_late=s, tau_s=tau_end / 2,

@@ -102,7 +102,9 @@ def test_512cubed_two_step_pass_equals_single_steps(prec):
 def test_planes_above_4gib_two_step_pass():
     """Planes above 4 GiB (FP64, 1024 x 1024 x 520: 4.36 GB per plane) take the two-step
     kernel's 64-bit addressing: three steps (a pair and a single step) equal single steps
-    in the 15-plane layout bit for bit."""
+    in the 15-plane layout bit for bit.  The read-only measuring pass also addresses them
+    in 64 bits: its windings equal those of the plain measuring kernel plaquette by
+    plaquette, and its sums agree to FP64 rounding."""
     print("CASE test=large_planes", flush=True)
     base = dict(precision=AH.AH_FP64, dx=0.5, dt=0.1, tau0=1.0, tau_ref=256.0, era_p=1.0,
                 s=1.0, seed=77)
@@ -113,6 +115,18 @@ def test_planes_above_4gib_two_step_pass():
         with AH.Context([p], [planes]) as c:
             c.step(3)
             runs.append(c.fields().clone())
+            if layout == AH.AH_LAYOUT_20:
+                (ot,), (wt,) = c.measure(wind=True)
+                c.set_kernel(AH.AH_KERNEL_PLAIN)
+                (op,), (wp,) = c.measure(wind=True)
+                assert torch.equal(wt, wp)
+                assert ot.n_wind == op.n_wind and ot.n_wind > 0
+                assert ot.length == op.length
+                # the parts of the energy, against the total
+                for k in ("energy", "kin", "grad", "elec", "mag", "pot"):
+                    assert abs(getattr(ot, k) - getattr(op, k)) <= 1e-12 * op.energy, k
+                assert list(ot.v2) == pytest.approx(list(op.v2), abs=1e-9)
+                del wt, wp
         del planes
         torch.cuda.empty_cache()
     assert torch.equal(runs[0], runs[1])
