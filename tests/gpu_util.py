@@ -1,5 +1,6 @@
-"""Helpers of the GPU tests: move seeded states in and out of the library's
-buffers and compare with the oracle.  Imported only by GPU tests."""
+"""Helpers of the tests that compare the library with the oracle: move seeded
+states in and out of the library's buffers, and cut a site's neighbourhood out
+of a state for the oracle.  No GPU call is made by importing it."""
 from __future__ import annotations
 
 import numpy as np
@@ -60,3 +61,30 @@ def plaquette_touches(amb: np.ndarray) -> np.ndarray:
     yz = ly | lz | sh(lz, 1) | sh(ly, 0)
     zx = lz | lx | sh(lx, 0) | sh(lz, 2)
     return np.stack([xy, yz, zx])
+
+
+def small_params(O, p, L):
+    """The oracle's parameters of p on an L^3 periodic lattice."""
+    return O.Params(L, L, L, dx=p.dx, dt=p.dt, tau0=p.tau0, tau_ref=p.tau_ref, era_p=p.era_p,
+                    s=p.s, lambda0=p.lambda0, e0=p.e0, sigma=p.sigma, seed=p.seed,
+                    s_late=p.s_late, tau_s=p.tau_s)
+
+
+def neighbourhoods(F, xyz, r):
+    """For each site (x, y, z) of xyz, the state within r sites of it (Chebyshev) and one
+    more layer, as an L^3 periodic lattice with L = 2r + 2 and the site at (r, r, r):
+    array (k, 10, L, L, L) in FP64.  A site's update depends on its neighbours and the
+    other corners of its plaquettes only, so on this lattice the oracle advances the
+    site by one step exactly as on the whole lattice for r = 1, and by two for r = 2."""
+    n = F.shape[-1]
+    off = torch.arange(-r, r + 2, device=F.device)
+    t = torch.as_tensor(xyz, device=F.device)
+    X, Y, Z = [(t[:, k, None] + off) % n for k in range(3)]
+    g = F[:, Z[:, :, None, None], Y[:, None, :, None], X[:, None, None, :]]
+    return g.permute(1, 0, 2, 3, 4).double().cpu().numpy()
+
+
+def site_values(F, xyz):
+    """(k, 10) FP64: the state at the given sites."""
+    t = torch.as_tensor(xyz, device=F.device)
+    return F[:, t[:, 2], t[:, 1], t[:, 0]].T.double().cpu().numpy()

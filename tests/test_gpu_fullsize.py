@@ -4,6 +4,10 @@
   evaluated site by site on sampled sites (tile edges in x and y, z-chunk
   edges, lattice boundaries, random interior sites), FP32 and FP64; and the
   two-steps-per-pass kernel against single steps, bit for bit.
+- 1024^3 FP32, radiation era, s = 1 (the largest configuration) in its
+  production launch shape: the read-only pass's windings, one pair and one
+  single step against the oracle on sampled sites, each evaluated on a small
+  periodic lattice holding the site's neighbourhood.
 - 1024 x 1024 x 128 (one GPU's share of 1024^3 over 8 GPUs, bench.py's slab
   form): the slab with halo planes closed on itself against the periodic
   lattice, bit for bit.
@@ -29,7 +33,8 @@ pytestmark = pytest.mark.gpu
 
 AH = pytest.importorskip("paper_1809_00995_amd")
 from tests.gpu_util import (ambiguous_links, fields_np, group_errors,  # noqa: E402
-                            oracle_params, plaquette_touches)
+                            neighbourhoods, oracle_params, plaquette_touches, site_values,
+                            small_params)
 
 
 def _edge_coords(n, period):
@@ -130,6 +135,94 @@ def test_planes_above_4gib_two_step_pass():
         del planes
         torch.cuda.empty_cache()
     assert torch.equal(runs[0], runs[1])
+
+
+def _sample_xyz(n, rng, periods_xy, periods_z, k_random):
+    xs = _edge_coords(n, 64)
+    ys = sorted({c for per in periods_xy for c in _edge_coords(n, per)})
+    zs = sorted({c for per in periods_z for c in _edge_coords(n, per)})
+    pts = [(int(rng.choice(xs)), int(rng.choice(ys)), int(rng.choice(zs))) for _ in range(k_random)]
+    pts += [tuple(int(v) for v in rng.integers(0, n, size=3)) for _ in range(k_random)]
+    return np.unique(np.array(pts, dtype=np.int64), axis=0)
+
+
+def _check_groups(got, ref, tol, what):
+    for g, cols in (("phi", [0, 1]), ("pi", [2, 3]), ("a", [4, 5, 6]), ("e", [7, 8, 9])):
+        scale = np.abs(ref[:, cols]).max()
+        err = np.abs(got[:, cols] - ref[:, cols]).max() / scale
+        print(f"  {what} {g}: max rel err {err:.2e} over {len(got)} sites", flush=True)
+        assert err < tol, (what, g)
+
+
+def test_1024cubed_fp32_production_path(O):
+    """The largest configuration, 1024^3 FP32 in the radiation era with s = 1 (85.9 GB in
+    the 20-plane layout), in the launch shape the library takes for it: pairs of steps in
+    z-chunks of at most 192 planes, the read-only measuring pass on 4 GiB planes (32-bit
+    offsets), odd steps by the single-step kernel.  From the random-phase start, 64 steps
+    with diagnostics every 64 steps; then, on sampled sites next to every tile and chunk
+    edge and at random, each against the oracle evaluated on the site's neighbourhood:
+    - the windings of the read-only pass at S_64 (plaquettes with a link within 1e-6 of
+      the branch cut aside), whose whole map also equals the plain measuring kernel's
+      and nets to zero in every orientation;
+    - one pair (S_64 -> S_66) and one single step (S_66 -> S_67), to 1e-5 per field
+      group (FP32 arithmetic from FP32 states against FP64)."""
+    n = 1024
+    print("CASE test=1024_fp32", flush=True)
+    p = AH.Params(n, n, n, precision=AH.AH_FP32, dx=0.5, dt=0.1, tau0=0.0, tau_ref=256.0,
+                  era_p=1.0, s=1.0, seed=1025)
+    planes = AH.alloc_planes(p)
+    rng = np.random.default_rng(11)
+    with AH.Context([p], [planes]) as c:
+        obs = c.step(64, measure_every=64)
+        assert len(obs) == 1 and obs[0][0].step == 0
+        # the read-only pass at S_64 against the plain kernel and the oracle
+        (ot,), (wt,) = c.measure(wind=True)
+        c.set_kernel(AH.AH_KERNEL_PLAIN)
+        (op,), (wp,) = c.measure(wind=True)
+        c.set_kernel(AH.AH_KERNEL_AUTO)
+        assert torch.equal(wt, wp)
+        assert ot.n_wind == op.n_wind and ot.n_wind > 0
+        assert list(ot.net_wind_dir) == [0, 0, 0]
+        F = c.fields()
+        xyz_w = _sample_xyz(n, rng, (4, 8, 9), (128, 171, 192, 205, 512), 300)
+        nb = neighbourhoods(F, xyz_w, 1)
+        t = torch.as_tensor(xyz_w, device=wt.device)
+        w_gpu = wt[:, t[:, 2], t[:, 1], t[:, 0]].T.cpu().numpy()
+        del wt, wp
+        sp4 = small_params(O, p, 4)
+        checked = 0
+        for k in range(len(xyz_w)):
+            ref = O.measure(sp4, 64, nb[k], wind_map=True).wind[:, 1, 1, 1]
+            amb = plaquette_touches(ambiguous_links(nb[k]))[:, 1, 1, 1]
+            ok = ~amb
+            assert np.array_equal(w_gpu[k][ok], ref[ok]), (xyz_w[k], w_gpu[k], ref)
+            checked += int(ok.sum())
+        print(f"  windings: {checked} sampled plaquettes equal the oracle's", flush=True)
+        # one pair, S_64 -> S_66
+        xyz_2 = _sample_xyz(n, rng, (9,), (128, 171, 192, 205), 250)
+        nb2 = neighbourhoods(F, xyz_2, 2)
+        del F
+        c.step(2)
+        F = c.fields()
+        got2 = site_values(F, xyz_2)
+        sp6 = small_params(O, p, 6)
+        mid = 2 + 6 * (2 + 6 * 2)
+        ref2 = np.stack([O.step_sites(sp6, 65, O.step(sp6, 64, nb2[k]), [mid])[0]
+                         for k in range(len(xyz_2))])
+        _check_groups(got2, ref2, 1e-5, "pair")
+        # one single step, S_66 -> S_67
+        xyz_1 = _sample_xyz(n, rng, (8,), (512, 128), 250)
+        nb1 = neighbourhoods(F, xyz_1, 1)
+        del F
+        c.step(1)
+        F = c.fields()
+        got1 = site_values(F, xyz_1)
+        del F
+        mid = 1 + 4 * (1 + 4 * 1)
+        ref1 = np.stack([O.step_sites(sp4, 66, nb1[k], [mid])[0] for k in range(len(xyz_1))])
+        _check_groups(got1, ref1, 1e-5, "single step")
+    del planes
+    torch.cuda.empty_cache()
 
 
 def test_slab_1024x1024x128_equals_periodic():
