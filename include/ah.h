@@ -17,6 +17,10 @@
  *    one torch tensor per realization) and must outlive the context.  The
  *    library owns only its small scratch (step counters, coefficients,
  *    reduction accumulators), allocated in ah_init and released in ah_free.
+ *    The accumulators hold 64 measured states per realization; an ah_step
+ *    call that measures more states at once grows them (at least doubling),
+ *    the only allocation a step call makes apart from the one-time work
+ *    lists and graphs of the batched form (ah_set_launch).
  *  - Streams: every GPU operation of a context is issued on the hipStream_t
  *    given to ah_init (NULL = the default stream).  ah_step is asynchronous
  *    unless it returns observations; ah_measure and ah_gauss_residual

@@ -4,4 +4,4 @@ from . import ah  # noqa: F401
 from .ah import (AH_FP32, AH_FP64, AH_INIT_NONE, AH_INIT_RANDOM_PHASE,  # noqa: F401
                  AH_INIT_VACUUM, AH_KERNEL_AUTO, AH_KERNEL_PLAIN, AH_KERNEL_TILED,
                  AH_KERNEL_TILED2, AH_LAYOUT_15, AH_LAYOUT_20, AHError, Context, Obs, Params,
-                 alloc_planes, load_library, measure_noalloc, obs_from_bytes)
+                 ObsRecords, alloc_planes, load_library, measure_noalloc, obs_from_bytes)

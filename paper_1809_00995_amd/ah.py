@@ -12,6 +12,7 @@ import os
 from dataclasses import dataclass, field
 from typing import Sequence
 
+import numpy as np
 import torch
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libah.so")
@@ -192,6 +193,31 @@ class Obs:
         return Obs(**d)
 
 
+class ObsRecords:
+    """Undecoded observations of one ah_step call: n_slots measured states of n_real
+    realizations each."""
+
+    def __init__(self, records, n_slots: int, n_real: int):
+        self.records, self.n_slots, self.n_real = records, n_slots, n_real
+
+    def __len__(self) -> int:
+        return self.n_slots
+
+    def decode(self) -> list:
+        """The observations as a list of per-slot lists of Obs."""
+        flat = _obs_list(self.records, self.n_slots * self.n_real)
+        return [flat[j * self.n_real:(j + 1) * self.n_real] for j in range(self.n_slots)]
+
+
+def _obs_list(records, n: int) -> list:
+    """The first n ah_obs of a ctypes array as Obs, read in one pass (a field-by-field
+    ctypes read costs tens of microseconds per record)."""
+    if n <= 0:
+        return []
+    rows = np.ctypeslib.as_array(records)[:n].tolist()
+    return [Obs(*[v.tolist() if isinstance(v, np.ndarray) else v for v in row]) for row in rows]
+
+
 def alloc_planes(p: Params, device="cuda") -> torch.Tensor:
     """Caller-owned field storage: 15 or 20 planes by layout (see include/ah.h), shape
     (planes, nz + 2 z_halo, ny, nx)."""
@@ -266,8 +292,11 @@ class Context:
     def n_real(self) -> int:
         return len(self.params)
 
-    def step(self, nsteps: int, measure_every: int = 0, out_cap: int | None = None):
-        """Advance nsteps; returns the observations (list of per-slot lists) when measuring."""
+    def step(self, nsteps: int, measure_every: int = 0, out_cap: int | None = None,
+             decode: bool = True):
+        """Advance nsteps; returns the observations (list of per-slot lists) when measuring.
+        With decode=False the records come back undecoded (an ObsRecords; its decode()
+        gives the same lists), which keeps Python object construction out of the call."""
         if measure_every <= 0:
             rc = self.lib.ah_step(self._ctx, nsteps, 0, None, 0, None)
             _check(self.lib, self._ctx, rc)
@@ -276,12 +305,11 @@ class Context:
         out = (_Obs * (cap * self.n_real))()
         n_out = C.c_int64()
         rc = self.lib.ah_step(self._ctx, nsteps, measure_every, out, cap, C.byref(n_out))
-        res = [[Obs._from(out[j * self.n_real + r]) for r in range(self.n_real)]
-               for j in range(n_out.value)]
         if rc == AH_E_NONFINITE:
             raise AHError(rc, self.lib.ah_last_error(self._ctx).decode())
         _check(self.lib, self._ctx, rc)
-        return res
+        rec = ObsRecords(out, n_out.value, self.n_real)
+        return rec.decode() if decode else rec
 
     def measure(self, wind: bool = False):
         """Observations of the current state; with wind=True also the W maps (int8, device)."""
@@ -295,7 +323,7 @@ class Context:
         rc = self.lib.ah_measure(self._ctx, out,
                                  C.c_void_p(wmap.data_ptr()) if wmap is not None else None)
         _check(self.lib, self._ctx, rc)
-        obs = [Obs._from(out[r]) for r in range(self.n_real)]
+        obs = _obs_list(out, self.n_real)
         if not wind:
             return obs
         maps, off = [], 0

@@ -206,9 +206,15 @@ void invalidate_plans(ah_ctx *c) {
     c->gexec_valid = false;
 }
 
+// Measurement slots for at least `states` measured states of every realization.
+// The context starts with kMinSlotStates (ah_init), so calls that measure up to
+// that many states never allocate; beyond it the capacity at least doubles.
+constexpr int64_t kMinSlotStates = 64;
+
 int ensure_slots(ah_ctx *c, int64_t states) {
     if (states <= c->slot_cap)
         return AH_OK;
+    states = std::max(states, std::max(2 * c->slot_cap, kMinSlotStates));
     if (c->d_slots)
         (void)hipFree(c->d_slots);
     if (c->d_obs)
@@ -782,6 +788,11 @@ int ah_init(ah_ctx **out, int32_t n_real, const ah_params *p, const ah_buffers *
         if ((e = hipGetLastError()) != hipSuccess)
             return hip_fail(e, "k_init launch");
     }
+    if ((e = hipMalloc(&c->d_slots, kMinSlotStates * n_real * sizeof(Slot))) != hipSuccess)
+        return hip_fail(e, "hipMalloc(slots)");
+    if ((e = hipMalloc(&c->d_obs, kMinSlotStates * n_real * sizeof(ah_obs))) != hipSuccess)
+        return hip_fail(e, "hipMalloc(obs)");
+    c->slot_cap = kMinSlotStates;
     // the host vectors above are stack memory: make sure the copies are done
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess)
         return hip_fail(e, "hipStreamSynchronize");

@@ -160,3 +160,32 @@ def test_bench_refuses_more_than_one_gpu():
                          capture_output=True, text=True, timeout=120)
     assert res.returncode == 2
     assert "one GPU" in res.stderr and res.stdout == ""
+
+
+def test_observation_records_decode_like_field_by_field_reads():
+    """ObsRecords.decode (one NumPy pass over the ah_obs array) gives the Obs a
+    field-by-field ctypes read gives, for every field kind: integers, doubles,
+    NaN, and the fixed-size arrays."""
+    n_slots, n_real = 3, 5
+    out = (B._Obs * (n_slots * n_real))()
+    for k in range(n_slots * n_real):
+        o = out[k]
+        o.step, o.tau, o.a, o.n_wind = 20 * k, 0.1 * k + 1.0, 2.0 ** -k, 7 * k - 3
+        o.n_wind_dir[2], o.net_wind_dir[0], o.nonfinite = k, -k, k % 2
+        o.v2[1], o.num[0], o.den[2] = 0.25 * k, -1e300, 3e-310
+        o.xi_l = float("nan") if k % 3 == 0 else 1.5 * k
+        o.energy, o.pres_lag, o.v2_eos = -0.5 * k, 1e-17 * k, 0.3
+    rec = B.ObsRecords(out, n_slots, n_real)
+    got = rec.decode()
+    assert len(rec) == n_slots and [len(s) for s in got] == [n_real] * n_slots
+    for j in range(n_slots):
+        for r in range(n_real):
+            ref = B.Obs._from(out[j * n_real + r])
+            g = got[j][r]
+            for name in B.Obs.__dataclass_fields__:
+                a, b = getattr(g, name), getattr(ref, name)
+                assert type(a) is type(b), name
+                if isinstance(b, float) and b != b:
+                    assert a != a, name
+                else:
+                    assert a == b, name
