@@ -78,7 +78,9 @@ def run_form(AH, torch, n, prec, kernel, steps, warmup, layout=15, s=0.0):
     if kernel != AH.AH_KERNEL_AUTO:
         ctx.set_kernel(kernel)
     stream = ctx.stream
-    ctx.step(warmup)
+    # the warmup steps take the measurement cadence too, so that every path the timed
+    # region takes (the measuring kernels, the observations' return) has run once
+    ctx.step(warmup, measure_every=MEASURE_EVERY)
     # with pairs, the timed region starts on an even step (one more untimed step when
     # the warmup count is odd), so that it takes the same passes as the steady state
     # of a long run: pairs, and at each measured state the read-only pass
@@ -299,6 +301,24 @@ def run_ensemble(AH, torch, batched, graph_steps, tune, layout=20):
     return total / sec, sec, tuning
 
 
+def gpu_warmup(AH, torch, n, layout, seconds=0.5):
+    """About `seconds` of the workload (steps with the measurement cadence) on a scratch
+    n^3 FP32 lattice, untimed, before the first timed form.  Measured on one GPU: after
+    the device-copy warm-up alone the first form timed in a process ran 4-7 % below the
+    same form timed again (its passes 2-4 % slower); after this warm-up the two agree
+    within 0.5 %.  A warm-up of passes alone, without the measurements, left 2 %."""
+    p = AH.Params(n, n, n, precision=AH.AH_FP32, tau0=0.0, tau_ref=n * 0.25, era_p=2.0, s=0.0,
+                  seed=1, layout=AH.AH_LAYOUT_20 if layout == 20 else AH.AH_LAYOUT_15)
+    planes = AH.alloc_planes(p)
+    with AH.Context([p], [planes]) as ctx:
+        t = time.perf_counter()
+        while time.perf_counter() - t < seconds:
+            ctx.step(MEASURE_EVERY, measure_every=MEASURE_EVERY)
+            torch.cuda.synchronize()
+    del planes
+    torch.cuda.empty_cache()
+
+
 def device_copy_rate(torch, reps=200, timed=20):
     """GB/s (read + write) of a plain 1 GiB device-to-device copy on this GPU, the mean of
     the last `timed` of `reps` copies.  Run before the first timed form, the copies also
@@ -383,6 +403,7 @@ def main():
     other = 15 if args.layout == 20 else 20
 
     copy_gbs = device_copy_rate(torch)
+    gpu_warmup(AH, torch, n, args.layout)
     f32 = run_form(AH, torch, n, AH.AH_FP32, kern, K, W, args.layout)
     rate32, ms32, kms32, per32, last32 = (f32["rate"], f32["ms_per_step"], f32["kernel_ms"],
                                           f32["per"], f32["last"])
