@@ -43,40 +43,79 @@ constexpr long kTiled2Slots = 256;
 // 23.1 ms per pair, 4 of 256 23.8 ms, 5-7 of 205-147 planes 21.4-21.5 ms) and
 // at least 32 where nz allows.  For one launch over one realization, a block
 // walks its chunk at a pace set by its own compute unit, so the launch lasts
-// about (rounds of kTiled2Slots blocks) x (planes per chunk + 2); the longest
-// chunks within 1 % of the least such cost are taken (measured per pair:
-// FP64 512^3 171 -> 128 planes 6.49 -> 6.32 ms, FP64 384^3 77 -> 64 planes
-// 3.00 -> 2.79 ms, FP64 256^3 32 -> 43 planes 0.91 -> 0.85 ms, FP32 256^3
-// 32 -> 128 planes 0.40 -> 0.37 ms; FP32 512^3, 1024^3 and the 1024 x 1024 x
-// 128 slab keep 103, 171 and 64 planes).  Work lists of the batched launch
-// (one_launch = false) share the chip between realizations and aim at ~2048
-// blocks per realization instead.
-inline void tiled2_defaults(bool fp64, int nx, int ny, int nz, int &ty, int &cz,
-                            bool one_launch = true) {
-    if (ty <= 0) {
-        const long w = (long)nx * nz;
-        ty = tiled2_default_ty(fp64, &ny, &w, 1);
-    }
-    if (cz > 0)
-        return;
+// about (rounds of kTiled2Slots blocks) x (planes per chunk + 2) x (a block's
+// time per plane); the longest chunks within 1 % of the least such cost are
+// taken (measured per pair: FP64 512^3 171 -> 128 planes 6.49 -> 6.32 ms, FP64
+// 384^3 77 -> 64 planes 3.00 -> 2.79 ms, FP64 256^3 32 -> 43 planes 0.91 ->
+// 0.85 ms), and the lower tile height where that cost is more than 2 % below
+// the default height's (FP32, 9 -> 8 rows: 1024 x 1024 x 128 2.86 -> 2.74 ms,
+// 384^3 1.30 -> 1.22 ms, 256^3 0.364 -> 0.350 ms, 768^3 9.63 -> 9.34 ms; 512^3
+// and 1024^3 keep 9 rows and 103 and 171 planes).  Work lists of the batched
+// launch (one_launch = false) share the chip between realizations and aim at
+// ~2048 blocks per realization instead.
+// Chunk count of the one-launch cost model for tile height ty: the longest
+// chunks within 1 % of the least cost; *cost_out gets that cost, in plane
+// times of a block of the default height.
+inline long tiled2_chunks(bool fp64, int nx, int ny, int nz, int ty, double *cost_out) {
     const long tiles_xy = (long)(nx / 64) * ((ny + ty - 1) / ty);
     long lo = (nz + 191) / 192, hi = (nz + 31) / 32;
     if (lo < 1)
         lo = 1;
     if (hi < lo)
         hi = lo;
+    // a block's time per plane relative to one of the default height: its rows,
+    // and the 1.6 % (FP32, 8 against 9 rows) or 8.5 % (FP64, 4 against 5) more
+    // time per site that the relatively larger ring of the lower tile costs
+    const int big = fp64 ? 5 : 9;
+    const double per_block = ty == big ? 1.0 : (double)ty / big * (fp64 ? 1.085 : 1.016);
+    auto cost = [&](long k) {
+        const long len = (nz + k - 1) / k, used = (nz + len - 1) / len;
+        return (double)((tiles_xy * used + kTiled2Slots - 1) / kTiled2Slots) * (len + 2) *
+               per_block;
+    };
+    double least = cost(lo);
+    for (long k = lo + 1; k <= hi; ++k)
+        least = cost(k) < least ? cost(k) : least;
     long chunks = lo;
+    while (cost(chunks) > 1.01 * least)   // ends at the least-cost count at the latest
+        ++chunks;
+    if (cost_out)
+        *cost_out = cost(chunks);
+    return chunks;
+}
+
+inline void tiled2_defaults(bool fp64, int nx, int ny, int nz, int &ty, int &cz,
+                            bool one_launch = true) {
+    const bool ty_default = ty <= 0;
+    if (ty_default) {
+        const long w = (long)nx * nz;
+        ty = tiled2_default_ty(fp64, &ny, &w, 1);
+    }
+    if (cz > 0)
+        return;
+    long chunks;
     if (one_launch) {
-        auto cost = [&](long k) {
-            const long len = (nz + k - 1) / k, used = (nz + len - 1) / len;
-            return (double)((tiles_xy * used + kTiled2Slots - 1) / kTiled2Slots) * (len + 2);
-        };
-        double least = cost(lo);
-        for (long k = lo + 1; k <= hi; ++k)
-            least = cost(k) < least ? cost(k) : least;
-        while (cost(chunks) > 1.01 * least)   // ends at the least-cost count at the latest
-            ++chunks;
+        double c_ty = 0;
+        chunks = tiled2_chunks(fp64, nx, ny, nz, ty, &c_ty);
+        if (ty_default) {
+            // the other height when its rounds of blocks fit the chip more than 2 %
+            // better (a 1024 x 1024 x 128 slab: 2048 tiles of 8 rows are 8 full
+            // rounds, 1824 of 9 rows 7.1)
+            const int other = ty == (fp64 ? 5 : 9) ? ty - 1 : ty + 1;
+            double c_o = 0;
+            const long k_o = tiled2_chunks(fp64, nx, ny, nz, other, &c_o);
+            if (c_o < 0.98 * c_ty) {
+                ty = other;
+                chunks = k_o;
+            }
+        }
     } else {
+        const long tiles_xy = (long)(nx / 64) * ((ny + ty - 1) / ty);
+        long lo = (nz + 191) / 192, hi = (nz + 31) / 32;
+        if (lo < 1)
+            lo = 1;
+        if (hi < lo)
+            hi = lo;
         chunks = (2048 + tiles_xy - 1) / tiles_xy;
         chunks = chunks < lo ? lo : (chunks > hi ? hi : chunks);
     }

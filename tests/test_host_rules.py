@@ -4,8 +4,10 @@ compiled into a small host program and run on the CPU (no GPU call).
 Pinned: the default tile heights (9 FP32, 5 FP64 unless their ragged last rows
 idle 2 % more sites than one row less) and the default z-chunks: at most 192
 planes, and for one launch the longest chunks whose estimated cost,
-ceil(blocks / 256) x (planes per chunk + 2), is within 1 % of the least, against
-the values worked out by hand below.
+ceil(blocks / 256) x (planes per chunk + 2) x (a block's time per plane: 1 for the
+default height, 8/9 x 1.016 for 8 FP32 rows, 4/5 x 1.085 for 4 FP64 rows), is within
+1 % of the least, with the lower height taken when its cost is more than 2 % below
+the default height's; against the values worked out by hand below.
 """
 import os
 import shutil
@@ -58,8 +60,16 @@ def rules(tmp_path_factory):
 
 
 def test_tile_heights(rules):
+    """512^3 FP32: 8-row tiles (512 a plane) cost at best 4 chunks of 128, 8 rounds x 130
+    x 0.9031 = 939.2, not 2 % below the 945 of 9 rows: 9.  1024 x 1024 x 128 FP32: 9 rows
+    (1824 tiles) cost at best 15 x 66 = 990, 8 rows (2048 tiles, one chunk) 8 x 130 x
+    0.9031 = 939.2 < 0.98 x 990: 8.  256^3 FP32: 9 rows (116 tiles, 2 chunks) 1 x 130,
+    8 rows (128 tiles) 117.4 < 127.4: 8."""
     table, _ = rules
     assert table[(512, 512, 512, 0)][0] == 9 and table[(512, 512, 512, 1)][0] == 5
+    assert table[(1024, 1024, 1024, 0)][0] == 9
+    assert table[(1024, 1024, 128, 0)][0] == 8
+    assert table[(256, 256, 256, 0)][0] == 8
     # 128 rows: 9-row tiles pad to 135 (5.5 % idle), 8-row tiles none
     assert table[(128, 128, 128, 0)][0] == 8
     # 16 rows in FP64: 5-row tiles pad to 20 (25 %), 4-row tiles none
@@ -76,7 +86,7 @@ def test_chunks_for_one_launch(rules):
     assert table[(512, 512, 512, 1)][1] == 128
     assert table[(512, 512, 512, 0)][1] == 103
     assert table[(1024, 1024, 1024, 0)][1] == 171
-    assert table[(1024, 1024, 128, 0)][1] == 64
+    assert table[(1024, 1024, 128, 0)][1] == 128
     assert table[(256, 256, 256, 0)][1] == 128
     assert table[(256, 256, 256, 1)][1] == 43
     # a lattice shorter than 32 planes is one chunk
