@@ -301,6 +301,18 @@ def run_ensemble(AH, torch, batched, graph_steps, tune, layout=20):
     return total / sec, sec, tuning
 
 
+def secondary(line, name, fn):
+    """line[name] = fn(); a form that fails records its error instead, so that the
+    headline line is printed whatever happens to the forms after it."""
+    try:
+        line[name] = fn()
+    except (Exception, SystemExit) as e:      # run_form exits on too few steps
+        line[name] = {"error": f"{type(e).__name__}: {e}"}
+    v = line[name].get("value")
+    print(f"# {name}: " + (f"{v:.4g} site-updates/s" if v is not None else line[name]["error"]),
+          file=sys.stderr, flush=True)
+
+
 def gpu_warmup(AH, torch, n, layout, seconds=0.5):
     """About `seconds` of the workload (steps with the measurement cadence) on a scratch
     n^3 FP32 lattice, untimed, before the first timed form.  Measured on one GPU: after
@@ -466,47 +478,28 @@ def main():
     if last32 is not None:
         line["last_obs"] = {"step": last32.step, "n_wind": last32.n_wind,
                             "xi_w": last32.xi_w, "v2_L": last32.v2[0]}
-    if not args.no_secondary:
-        forms = [("fp32_layout%d" % other, AH.AH_FP32, kern, K, W, other, "f32"),
-                 ("fp64", AH.AH_FP64, kern, K, W, args.layout, "f64"),
-                 ("fp64_layout%d" % other, AH.AH_FP64, kern, K, W, other, "f64")]
-        for name, prec, kk, steps, warm, lay, dt in forms:
-            f = run_form(AH, torch, n, prec, kk, steps, warm, lay)
-            print(f"# {name}: {f['rate']:.4g} site-updates/s", file=sys.stderr, flush=True)
-            ach = BYTES_PER_SITE[dt] * n ** 3 * f["per"] / (f["kernel_ms"] * 1e-3) / 1e9
-            line[name] = {"value": f["rate"], "ms_per_step": f["ms_per_step"],
-                          "value_without_diagnostics": f["rate_no_diag"],
-                          "kernel_ms": f["kernel_ms"], "steps_per_launch": f["per"],
-                          "layout": lay, "achieved_algorithmic_GBs": ach,
-                          "frac_algorithmic": ach / HBM_PEAK_GBS}
-        # the second leg of the 512^3 matter-era workload: s = 1 (true equations of motion)
-        f = run_form(AH, torch, n, AH.AH_FP32, kern, K, W, args.layout, s=1.0)
-        print(f"# fp32 s=1: {f['rate']:.4g} site-updates/s", file=sys.stderr, flush=True)
-        ach = BYTES_PER_SITE["f32"] * n ** 3 * f["per"] / (f["kernel_ms"] * 1e-3) / 1e9
-        line["fp32_s1"] = {"value": f["rate"], "ms_per_step": f["ms_per_step"],
-                           "value_without_diagnostics": f["rate_no_diag"],
-                           "kernel_ms": f["kernel_ms"], "steps_per_launch": f["per"],
-                           "layout": args.layout, "achieved_algorithmic_GBs": ach,
-                           "frac_algorithmic": ach / HBM_PEAK_GBS, "s": 1.0}
+    def form_entry(prec, kk, lay, dt, s=0.0):
+        f = run_form(AH, torch, n, prec, kk, K, W, lay, s=s)
+        ach = BYTES_PER_SITE[dt] * n ** 3 * f["per"] / (f["kernel_ms"] * 1e-3) / 1e9
+        e = {"value": f["rate"], "ms_per_step": f["ms_per_step"],
+             "value_without_diagnostics": f["rate_no_diag"], "kernel_ms": f["kernel_ms"],
+             "steps_per_launch": f["per"], "layout": lay, "achieved_algorithmic_GBs": ach,
+             "frac_algorithmic": ach / HBM_PEAK_GBS}
+        if s:
+            e["s"] = s
+        return e
+
+    def plain_entry():
         kp = max(10, K // 4)
         fp = run_form(AH, torch, n, AH.AH_FP64, AH.AH_KERNEL_PLAIN, kp, 2)
-        print(f"# fp64 plain: {fp['rate']:.4g} site-updates/s", file=sys.stderr, flush=True)
-        line["plain_fp64"] = {"value": fp["rate"], "ms_per_step": fp["ms_per_step"],
-                              "kernel_ms": fp["kernel_ms"], "steps": kp}
-        line["speedup_fp32_vs_plain_fp64"] = rate32 / fp["rate"]
-        line["speedup_fp64_vs_plain_fp64"] = line["fp64"]["value"] / fp["rate"]
-        line["slab"] = run_slab(AH, torch)
-        print(f"# slab: {line['slab']['value']:.4g} site-updates/s, kernel "
-              f"{line['slab']['kernel_ms']:.3f} ms + halo refill "
-              f"{line['slab']['halo_refill_ms']:.3f} ms per pass", file=sys.stderr, flush=True)
-    if not args.no_secondary and not args.no_ensemble:
+        return {"value": fp["rate"], "ms_per_step": fp["ms_per_step"],
+                "kernel_ms": fp["kernel_ms"], "steps": kp}
+
+    def ensemble_entry():
         rb, sb, tuning = run_ensemble(AH, torch, True, 10, True)
         rs, ss, _ = run_ensemble(AH, torch, False, 0, False)
         r15, s15, _ = run_ensemble(AH, torch, True, 10, True, layout=15)
-        print(f"# ensemble: batched+graph+tuned {rb:.4g} site-updates/s ({sb:.3f} s), "
-              f"per-realization launches {rs:.4g} ({ss:.3f} s), one step per pass "
-              f"{r15:.4g} ({s15:.3f} s)", file=sys.stderr, flush=True)
-        line["ensemble"] = {
+        return {
             "workload": "48 x 128^3 + 16 x 64^3 + 4 x 256^3 FP32, radiation s=1 / matter s=0 "
                         "alternating, each to tau_end = N dx / 2 (320 / 160 / 640 steps), "
                         f"diagnostics every {MEASURE_EVERY} steps",
@@ -519,6 +512,23 @@ def main():
             "per_realization_launches": {"value": rs, "seconds": ss},
             "speedup_vs_per_realization": rb / rs,
             "one_step_per_pass": {"value": r15, "seconds": s15, "layout": 15}}
+
+    if not args.no_secondary:
+        for name, prec, lay, dt in (("fp32_layout%d" % other, AH.AH_FP32, other, "f32"),
+                                    ("fp64", AH.AH_FP64, args.layout, "f64"),
+                                    ("fp64_layout%d" % other, AH.AH_FP64, other, "f64")):
+            secondary(line, name, lambda: form_entry(prec, kern, lay, dt))
+        # the second leg of the 512^3 matter-era workload: s = 1 (true equations of motion)
+        secondary(line, "fp32_s1", lambda: form_entry(AH.AH_FP32, kern, args.layout, "f32", s=1.0))
+        secondary(line, "plain_fp64", plain_entry)
+        if "value" in line["plain_fp64"]:
+            line["speedup_fp32_vs_plain_fp64"] = rate32 / line["plain_fp64"]["value"]
+            if "value" in line["fp64"]:
+                line["speedup_fp64_vs_plain_fp64"] = (line["fp64"]["value"]
+                                                      / line["plain_fp64"]["value"])
+        secondary(line, "slab", lambda: run_slab(AH, torch))
+    if not args.no_secondary and not args.no_ensemble:
+        secondary(line, "ensemble", ensemble_entry)
     line["roofline"]["copy_GBs"] = copy_gbs
     if traffic is not None:
         line["roofline"]["traffic_frac_of_copy"] = line["roofline"]["traffic_GBs"] / copy_gbs

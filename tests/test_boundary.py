@@ -189,3 +189,26 @@ def test_observation_records_decode_like_field_by_field_reads():
                     assert a != a, name
                 else:
                     assert a == b, name
+
+
+def test_bench_secondary_form_failure_keeps_the_line():
+    """A secondary form of bench.py that fails (an exception, or run_form's exit when too
+    few steps are given) records its error in its own entry; the forms after it and the
+    headline line are still produced."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+
+    def boom():
+        raise RuntimeError("out of memory")
+
+    def too_few():
+        raise SystemExit("bench.py: no unmeasured 2-step call to time the kernel by")
+
+    line = {}
+    bench.secondary(line, "a", boom)
+    bench.secondary(line, "b", too_few)
+    bench.secondary(line, "c", lambda: {"value": 1.0})
+    assert line["a"] == {"error": "RuntimeError: out of memory"}
+    assert line["b"]["error"].startswith("SystemExit: bench.py: no unmeasured")
+    assert line["c"] == {"value": 1.0}
