@@ -2,8 +2,9 @@
 
 - 512^3 (the benchmark workload): one step of the library against the oracle
   evaluated site by site on sampled sites (tile edges in x and y, z-chunk
-  edges, lattice boundaries, random interior sites), FP32 and FP64; and the
-  two-steps-per-pass kernel against single steps, bit for bit.
+  edges, lattice boundaries, random interior sites), FP32 and FP64; the
+  two-steps-per-pass kernel against single steps, bit for bit; and the whole
+  1280-step run (s = 0 and s = 1) against Gauss's law and zero net winding.
 - 1024^3 FP32, radiation era, s = 1 (the largest configuration) in its
   production launch shape: the read-only pass's windings, one pair and one
   single step against the oracle on sampled sites, each evaluated on a small
@@ -76,6 +77,36 @@ def test_512cubed_one_step_on_sampled_sites(O, prec):
         err = np.abs(got[:, cols] - ref[:, cols]).max() / scale
         print(f"  {g}: max rel err {err:.2e} over {idx.size} sites", flush=True)
         assert err < tol, g
+
+
+@pytest.mark.parametrize("s", [0.0, 1.0])
+def test_512cubed_full_run_keeps_gauss_law_and_zero_net_winding(s):
+    """The benchmark's workload at its full length: 512^3 FP32, matter era, from the
+    random-phase start to tau_end = 128 (1280 steps) with diagnostics every 20 steps, in
+    the production path (pairs, the read-only measuring pass), for both values of s.
+    Properties that hold at any size: every measurement finite with zero net winding in
+    each orientation (strings present at the start), and Gauss's law (Sec. 4) kept to the
+    FP32 rounding of the updates: each step rounds the E and Pi updates about ten times
+    at unit roundoff 6e-8 on terms of order one, so after 1280 steps the residual is below
+    10 x 6e-8 x 1280 = 7.7e-4 even if every rounding adds up (checked at 1e-3)."""
+    n, steps, every = 512, 1280, 20
+    print(f"CASE test=512_full_run s={s}", flush=True)
+    p = AH.Params(n, n, n, precision=AH.AH_FP32, dx=0.5, dt=0.1, tau0=0.0, tau_ref=n * 0.5 / 2,
+                  era_p=2.0, s=s, seed=2024)
+    planes = AH.alloc_planes(p)
+    with AH.Context([p], [planes]) as c:
+        obs = [o[0] for o in c.step(steps, measure_every=every)]
+        gmax, grms = c.gauss_residual()
+    del planes
+    torch.cuda.empty_cache()
+    assert [o.step for o in obs] == list(range(0, steps, every))
+    assert obs[0].n_wind > 0
+    for o in obs:
+        assert o.nonfinite == 0 and o.net_wind_dir == [0, 0, 0], o.step
+        assert math.isfinite(o.energy) and math.isfinite(o.length), o.step
+    print(f"  end: n_wind {obs[-1].n_wind}, xi_w {obs[-1].xi_w:.3f}; Gauss residual max "
+          f"{gmax[0]:.2e}, rms {grms[0]:.2e}", flush=True)
+    assert gmax[0] < 1e-3
 
 
 @pytest.mark.parametrize("prec", [AH.AH_FP32, AH.AH_FP64])
