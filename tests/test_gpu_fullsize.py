@@ -312,11 +312,14 @@ def _full_ensemble():
     return ps
 
 
-def test_full_ensemble_in_benchmark_launch_configuration():
+def test_full_ensemble_in_benchmark_launch_configuration(O):
     """The ensemble form as bench.py times it (autotuned tiles, one persistent launch
     per pair, 10-step graphs, diagnostics every 20 steps) equals one launch per
     realization bit for bit over 170 steps, past the n_end = 160 of the 64^3
-    realizations (frozen since), with the same winding counts and energies."""
+    realizations (frozen since), with the same winding counts and energies.  One more
+    batched pair then matches the oracle on sampled sites of a 128^3 matter-era and a
+    256^3 radiation-era realization (each site's neighbourhood on a 6^3 lattice, FP32
+    against FP64 from the same state: 1e-5 per field group)."""
     print("CASE test=full_ensemble", flush=True)
     ps = _full_ensemble()
     nsteps = 170
@@ -356,6 +359,28 @@ def test_full_ensemble_in_benchmark_launch_configuration():
             small = [r for r, p in enumerate(ps) if p.nx == 64]
             assert [got_obs[j][small[0]].step for j in range(len(got_obs))] == \
                 [0, 20, 40, 60, 80, 100, 120, 140, -1]
+            # one more batched pair against the oracle, on sampled sites (tile and
+            # lattice edges, random sites) of one active realization of each size
+            picks = [next(r for r, p in enumerate(ps) if p.nx == 128 and p.era_p == 2.0),
+                     next(r for r, p in enumerate(ps) if p.nx == 256 and p.era_p == 1.0)]
+            rng = np.random.default_rng(5)
+            cut = {}
+            for r in picks:
+                m = ps[r].nx
+                xyz = np.concatenate([rng.integers(0, m, size=(80, 3)),
+                                      [[0, 0, 0], [m - 1, m - 1, m - 1], [63, 64, m // 2],
+                                       [64, 7, 63], [m - 1, 8, 64]]])
+                xyz = np.unique(xyz, axis=0)
+                cut[r] = (xyz, neighbourhoods(got.fields(r), xyz, 2), got.current_step(r))
+            got.step(2)
+            mid6 = 2 + 6 * (2 + 6 * 2)
+            for r in picks:
+                xyz, nb, n0 = cut[r]
+                sp6 = small_params(O, ps[r], 6)
+                ref2 = np.stack([O.step_sites(sp6, n0 + 1, O.step(sp6, n0, nb[k]), [mid6])[0]
+                                 for k in range(len(xyz))])
+                _check_groups(site_values(got.fields(r), xyz), ref2, 1e-5,
+                              f"ensemble {ps[r].nx}^3")
         finally:
             got.close()
             del got_planes
