@@ -194,7 +194,8 @@ def test_1024cubed_fp32_production_path(O):
     edge and at random, each against the oracle evaluated on the site's neighbourhood:
     - the windings of the read-only pass at S_64 (plaquettes with a link within 1e-6 of
       the branch cut aside), whose whole map also equals the plain measuring kernel's
-      and nets to zero in every orientation;
+      and nets to zero in every orientation, and whose sums agree with that kernel's
+      FP64 densities to 1e-6 of the energy (<v^2> to 1e-5);
     - one pair (S_64 -> S_66) and one single step (S_66 -> S_67), to 1e-5 per field
       group (FP32 arithmetic from FP32 states against FP64)."""
     n = 1024
@@ -214,6 +215,12 @@ def test_1024cubed_fp32_production_path(O):
         assert torch.equal(wt, wp)
         assert ot.n_wind == op.n_wind and ot.n_wind > 0
         assert list(ot.net_wind_dir) == [0, 0, 0]
+        # the sums: FP32 densities (read-only pass) against FP64 ones (plain kernel) on
+        # the same state, 1e-6 of the total energy
+        for k in ("energy", "kin", "grad", "elec", "mag", "pot", "sum_lag"):
+            assert abs(getattr(ot, k) - getattr(op, k)) <= 1e-6 * op.energy, k
+        assert list(ot.v2) == pytest.approx(list(op.v2), abs=1e-5)
+        assert ot.v2_eos == pytest.approx(op.v2_eos, abs=1e-5)
         F = c.fields()
         xyz_w = _sample_xyz(n, rng, (4, 8, 9), (128, 171, 192, 205, 512), 300)
         nb = neighbourhoods(F, xyz_w, 1)
