@@ -76,10 +76,10 @@ def neighbourhoods(F, xyz, r):
     array (k, 10, L, L, L) in FP64.  A site's update depends on its neighbours and the
     other corners of its plaquettes only, so on this lattice the oracle advances the
     site by one step exactly as on the whole lattice for r = 1, and by two for r = 2."""
-    n = F.shape[-1]
+    ext = (F.shape[-1], F.shape[-2], F.shape[-3])      # nx, ny, nz
     off = torch.arange(-r, r + 2, device=F.device)
     t = torch.as_tensor(xyz, device=F.device)
-    X, Y, Z = [(t[:, k, None] + off) % n for k in range(3)]
+    X, Y, Z = [(t[:, k, None] + off) % ext[k] for k in range(3)]
     g = F[:, Z[:, :, None, None], Y[:, None, :, None], X[:, None, None, :]]
     return g.permute(1, 0, 2, 3, 4).double().cpu().numpy()
 

@@ -135,12 +135,14 @@ def test_512cubed_two_step_pass_equals_single_steps(prec):
         assert a.energy == pytest.approx(b.energy, rel=1e-12)
 
 
-def test_planes_above_4gib_two_step_pass():
+def test_planes_above_4gib_two_step_pass(O):
     """Planes above 4 GiB (FP64, 1024 x 1024 x 520: 4.36 GB per plane) take the two-step
     kernel's 64-bit addressing: three steps (a pair and a single step) equal single steps
-    in the 15-plane layout bit for bit.  The read-only measuring pass also addresses them
-    in 64 bits: its windings equal those of the plain measuring kernel plaquette by
-    plaquette, and its sums agree to FP64 rounding."""
+    in the 15-plane layout bit for bit, and one more pair matches the oracle (1e-12 per
+    field group) on sampled sites, among them sites past the 4 GiB offset (z >= 512),
+    each evaluated on its neighbourhood.  The read-only measuring pass also addresses
+    them in 64 bits: its windings equal those of the plain measuring kernel plaquette
+    by plaquette, and its sums agree to FP64 rounding."""
     print("CASE test=large_planes", flush=True)
     base = dict(precision=AH.AH_FP64, dx=0.5, dt=0.1, tau0=1.0, tau_ref=256.0, era_p=1.0,
                 s=1.0, seed=77)
@@ -163,6 +165,21 @@ def test_planes_above_4gib_two_step_pass():
                     assert abs(getattr(ot, k) - getattr(op, k)) <= 1e-12 * op.energy, k
                 assert list(ot.v2) == pytest.approx(list(op.v2), abs=1e-9)
                 del wt, wp
+                c.set_kernel(AH.AH_KERNEL_AUTO)
+                rng = np.random.default_rng(13)
+                xyz = np.concatenate([rng.integers(0, 1024, size=(60, 2)),
+                                      rng.integers(0, 520, size=(60, 1))], axis=1)
+                edge = [[0, 0, 511], [1023, 1023, 512], [64, 5, 519], [63, 1023, 0],
+                        [512, 512, 513], [1, 2, 518]]
+                xyz = np.unique(np.concatenate([xyz, edge]), axis=0)
+                nb = neighbourhoods(c.fields(), xyz, 2)
+                n0 = c.current_step(0)
+                c.step(2)
+                got = site_values(c.fields(), xyz)
+                sp6, mid6 = small_params(O, p, 6), 2 + 6 * (2 + 6 * 2)
+                ref = np.stack([O.step_sites(sp6, n0 + 1, O.step(sp6, n0, nb[k]), [mid6])[0]
+                                for k in range(len(xyz))])
+                _check_groups(got, ref, 1e-12, "pair past 4 GiB")
         del planes
         torch.cuda.empty_cache()
     assert torch.equal(runs[0], runs[1])
