@@ -280,11 +280,13 @@ def test_1024cubed_fp32_production_path(O):
     torch.cuda.empty_cache()
 
 
-def test_slab_1024x1024x128_equals_periodic():
+def test_slab_1024x1024x128_equals_periodic(O):
     """One GPU's share of 1024^3 over 8 GPUs, as bench.py times it: a 1024 x 1024 x 128
     FP32 slab with two halo planes a side, refilled before every pass from its own faces,
     equals the periodic 1024 x 1024 x 128 lattice bit for bit through pairs, a fused
-    measured step and a single step (the periodic kernels are pinned to the oracle above)."""
+    measured step and a single step; one more pair of the slab (8-row tiles, the halo
+    read through the refilled planes) matches the oracle on sampled sites, among them
+    sites next to the slab's faces (1e-5 per field group)."""
     print("CASE test=slab_1024", flush=True)
     nxy, nz, H = 1024, 128, 2
     base = dict(precision=AH.AH_FP32, dx=0.5, dt=0.1, tau0=1.0, tau_ref=256.0, era_p=1.0,
@@ -315,6 +317,20 @@ def test_slab_1024x1024x128_equals_periodic():
                 refill()
             assert slab.current_step() == ref.current_step() == 6
             assert torch.equal(slab.fields()[:, H:H + nz], ref.fields())
+            rng = np.random.default_rng(17)
+            xyz = np.concatenate([rng.integers(0, nxy, size=(60, 2)),
+                                  rng.integers(0, nz, size=(60, 1))], axis=1)
+            edge = [[0, 0, 0], [nxy - 1, nxy - 1, nz - 1], [64, 8, 0], [63, 7, nz - 1],
+                    [500, nxy - 8, 1], [700, 16, nz - 2]]
+            xyz = np.unique(np.concatenate([xyz, edge]), axis=0)
+            nb = neighbourhoods(ref.fields(), xyz, 2)
+            n0 = slab.current_step()
+            slab.step(2)
+            got = site_values(slab.fields()[:, H:H + nz], xyz)
+            sp6, mid6 = small_params(O, pp, 6), 2 + 6 * (2 + 6 * 2)
+            want = np.stack([O.step_sites(sp6, n0 + 1, O.step(sp6, n0, nb[k]), [mid6])[0]
+                             for k in range(len(xyz))])
+            _check_groups(got, want, 1e-5, "slab pair")
     del tp, ts
     torch.cuda.empty_cache()
 
