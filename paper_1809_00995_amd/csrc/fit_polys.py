@@ -1,11 +1,13 @@
 """Generator of the polynomial coefficients of the device sin/cos and arctangent
 (ah_device.hpp).
 
-sincos: the device reduces x by multiples of pi, x = k*pi + r with |r| <= pi/2,
-and evaluates
+sincos (double): the device reduces x by multiples of pi, x = k*pi + r with
+|r| <= pi/2, and evaluates
     sin r = r + r^3 * P(r^2),    cos r = 1 + r^2 * Q(r^2),
 flipping both signs for odd k.  P is the minimax fit (relative error of sin r)
-and Q the minimax fit (absolute error of cos r) on 0 <= r <= pi/2.
+and Q the minimax fit (absolute error of cos r) on 0 <= r <= pi/2.  The float
+sin/cos reduces by multiples of 2 pi and ends in the hardware sine and cosine;
+only its reduction constants are printed here.
 
 arctangent (FP32 phase of the winding filter): atan a = a + a^3 * T(a^2) on
 0 <= a <= 1 (the ratio of the smaller to the larger of |x|, |y|), minimax in
@@ -101,16 +103,16 @@ def rounded(v, name):
 
 
 def main():
-    for name, ns, nc in (("float", 4, 5), ("double", 8, 8)):
-        ps, es, pc, ec = fit(ns, nc)
-        print(f"// {name}: sin rel. error {mp.nstr(es, 3)}, cos abs. error {mp.nstr(ec, 3)}")
-        print("P (r^0 first):", ", ".join(rounded(v, name) for v in ps))
-        print("Q (r^0 first):", ", ".join(rounded(v, name) for v in pc))
-        hi = np.float32(float(mp.pi)) if name == "float" else float(mp.pi)
-        lo = mp.pi - mp.mpf(float(hi))
-        print("1/pi, pi high, pi low:", rounded(1 / mp.pi, name), rounded(mp.mpf(float(hi)), name),
-              rounded(lo, name))
-
+    ps, es, pc, ec = fit(8, 8)
+    print(f"// double: sin rel. error {mp.nstr(es, 3)}, cos abs. error {mp.nstr(ec, 3)}")
+    print("P (r^0 first):", ", ".join(rounded(v, "double") for v in ps))
+    print("Q (r^0 first):", ", ".join(rounded(v, "double") for v in pc))
+    lo = mp.pi - mp.mpf(float(mp.pi))
+    print("1/pi, pi high, pi low:", rounded(1 / mp.pi, "double"), rounded(mp.pi, "double"),
+          rounded(lo, "double"))
+    hi = mp.mpf(float(np.float32(float(2 * mp.pi))))
+    print("// float: 1/(2 pi), 2 pi high, 2 pi low:", rounded(1 / (2 * mp.pi), "float"),
+          rounded(hi, "float"), rounded(2 * mp.pi - hi, "float"))
 
     pa, ea = fit_atan(7)
     print(f"// float arctangent: rel. error {mp.nstr(ea, 3)}")

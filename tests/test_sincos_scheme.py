@@ -1,13 +1,14 @@
 """The device sin/cos of the link phasors and the FP32 phase of the winding filter
 (ah_device.hpp), checked on the CPU.
 
-The constants are read from the header and the scheme (reduction by multiples
-of pi in two fused multiply-adds, odd and even minimax polynomials, sign flip
-for odd multiples) is replayed with every operation rounded to the working
-precision: float32 through numpy with fused multiply-adds taken exactly in
-float64 and rounded once; float64 through mpmath at 60 digits, rounded once per
-operation.  A mistyped coefficient or a wrong sign shows up as an error far
-above the bounds stated in the header.
+The constants are read from the header and each scheme is replayed with every
+operation rounded to the working precision: float32 through numpy with fused
+multiply-adds taken exactly in float64 and rounded once; float64 through mpmath
+at 60 digits, rounded once per operation.  The double sin/cos (reduction by
+multiples of pi in two fused multiply-adds, odd and even minimax polynomials,
+sign flip for odd multiples) is replayed whole; of the float sin/cos, which ends
+in the hardware sine and cosine, the reduction.  A mistyped coefficient or a
+wrong sign shows up as an error far above the bounds stated in the header.
 """
 import os
 import re
@@ -37,8 +38,10 @@ def _split(vals, n_p):
     return inv_pi, hi, lo, p, q
 
 
-def _sincos_f32(x, consts):
-    inv_pi, hi, lo, p, q = consts
+def _reduce_f32(x, inv_2pi, hi, lo, inv_2pi_t):
+    """The float reduction, every operation rounded to float32 (the fused
+    multiply-adds taken exactly in float64 and rounded once): t = r / 2 pi in
+    revolutions with x = 2 pi k + r."""
     f32 = np.float32
 
     def fma(a, b, c):
@@ -46,41 +49,44 @@ def _sincos_f32(x, consts):
                 + np.asarray(c, np.float64)).astype(f32)
 
     x = x.astype(f32)
-    k = np.rint((x * f32(inv_pi)).astype(f32))
+    k = np.rint((x * f32(inv_2pi)).astype(f32))
     r = fma(-k, f32(hi), x)
     r = fma(-k, f32(lo), r)
-    u = (r * r).astype(f32)
-    ps = fma(u, f32(p[0]), f32(p[1]))
-    for c in p[2:]:
-        ps = fma(u, ps, f32(c))
-    s = fma((r * u).astype(f32), ps, r)
-    qs = fma(u, f32(q[0]), f32(q[1]))
-    for c in q[2:]:
-        qs = fma(u, qs, f32(c))
-    co = fma(u, qs, f32(1.0))
-    odd = (k.astype(np.int64) & 1) == 1
-    return np.where(odd, -s, s), np.where(odd, -co, co)
+    return k, (r * f32(inv_2pi_t)).astype(f32)
 
 
-def test_float_sincos_within_stated_error():
+def test_float_reduction_constants_and_error():
+    """The float sin/cos reduces by multiples of 2 pi (2 pi split into a float
+    high part and the float nearest the rest) and passes revolutions to the
+    hardware sine and cosine, whose own error is measured on the GPU
+    (test_gpu_sincos).  Here: the constants, and the reduction's share of the
+    error (2 pi t against x - 2 pi k in exact arithmetic) within the bound its
+    roundings give, for angles far beyond those the links hold."""
     vals = _constants("float")
-    assert len(vals) == 3 + 4 + 5 + 1
-    consts = _split(vals, 4)
+    assert len(vals) == 4
+    inv_2pi, hi, lo, inv_2pi_t = vals
+    two_pi = 2 * np.pi
+    assert np.float32(inv_2pi) == np.float32(1 / two_pi) and inv_2pi_t == inv_2pi
+    assert np.float32(hi) == np.float32(two_pi)
+    assert np.float32(lo) == np.float32(two_pi - float(np.float32(two_pi)))
     rng = np.random.default_rng(5)
-    for lim in (2.0, 40.0, 1e5):
+    for lim in (2.0, 40.0, 1e3):
         x = rng.uniform(-lim, lim, 400_000).astype(np.float32)
-        s, c = _sincos_f32(x, consts)
-        xd = x.astype(np.float64)
-        assert np.abs(s - np.sin(xd)).max() < 1.5e-7, lim
-        assert np.abs(c - np.cos(xd)).max() < 1.5e-7, lim
-    # exact special cases and symmetry
+        k, t = _reduce_f32(x, inv_2pi, hi, lo, inv_2pi_t)
+        # k rounds the float x / (2 pi), off by a few ulps of it near half-integers
+        assert np.abs(t).max() <= 0.5 + lim / (2 * np.pi) * 2.0 ** -22, lim
+        # x - 2 pi k in (nearly) exact arithmetic: float64 with 2 pi to 2^-52
+        exact = x.astype(np.float64) - k.astype(np.float64) * two_pi
+        err = np.abs(two_pi * t.astype(np.float64) - exact).max()
+        # two roundings of r (half an ulp of 4 each), the float 1/(2 pi) (relative
+        # error 4.0e-8, times |r| <= pi) and the rounding of t (half an ulp of 1/2)
+        assert err < 2 * 2.0 ** -22 + 4.04e-8 * np.pi + 2 * np.pi * 2.0 ** -26, (lim, err)
     z = np.array([0.0, -0.0], np.float32)
-    s, c = _sincos_f32(z, consts)
-    assert np.all(s == 0) and np.all(c == 1)
+    assert np.all(_reduce_f32(z, inv_2pi, hi, lo, inv_2pi_t)[1] == 0)
     x = rng.uniform(-30, 30, 10_000).astype(np.float32)
-    s1, c1 = _sincos_f32(x, consts)
-    s2, c2 = _sincos_f32(-x, consts)
-    assert np.array_equal(s1, -s2) and np.array_equal(c1, c2)
+    t1 = _reduce_f32(x, inv_2pi, hi, lo, inv_2pi_t)[1]
+    t2 = _reduce_f32(-x, inv_2pi, hi, lo, inv_2pi_t)[1]
+    assert np.array_equal(t1, -t2)
 
 
 def test_double_sincos_within_stated_error():
