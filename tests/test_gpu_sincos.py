@@ -41,7 +41,7 @@ def _link_state(lim, seed, odd_phi_imag):
 
 
 @pytest.mark.parametrize("kernel", [AH.AH_KERNEL_PLAIN, AH.AH_KERNEL_TILED], ids=["plain", "tiled"])
-@pytest.mark.parametrize("lim", [4.0, 100.0])
+@pytest.mark.parametrize("lim", [4.0, 100.0, 1e4])
 @pytest.mark.parametrize("fn", ["sin", "cos"])
 def test_link_phasors_within_stated_error(O, kernel, lim, fn):
     print("CASE test=link_phasors kernel", kernel, "lim", lim, "fn", fn, flush=True)

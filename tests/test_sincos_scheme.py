@@ -70,7 +70,7 @@ def test_float_reduction_constants_and_error():
     assert np.float32(hi) == np.float32(two_pi)
     assert np.float32(lo) == np.float32(two_pi - float(np.float32(two_pi)))
     rng = np.random.default_rng(5)
-    for lim in (2.0, 40.0, 1e3):
+    for lim in (2.0, 40.0, 1e3, 1e4):
         x = rng.uniform(-lim, lim, 400_000).astype(np.float32)
         k, t = _reduce_f32(x, inv_2pi, hi, lo, inv_2pi_t)
         # k rounds the float x / (2 pi), off by a few ulps of it near half-integers
