@@ -1,7 +1,8 @@
 """Seeded synthetic field states shared by the oracle tests and the GPU parity tests.
 
-This module only draws numbers: it holds none of the method's arithmetic (no
-update, no diagnostic).  Arrays have shape (10, nz, ny, nx) in the plane order
+This module draws numbers and maps a state through a lattice gauge
+transformation (a symmetry the tests check, not a step of the method): it holds
+none of the method's arithmetic (no update, no diagnostic).  Arrays have shape (10, nz, ny, nx) in the plane order
 phi_re, phi_im, Pi_re, Pi_im, A_x, A_y, A_z, E_x, E_y, E_z.
 """
 from __future__ import annotations
@@ -50,6 +51,20 @@ def smooth_state(n: int, seed: int, modes: int = 2, amp=0.3) -> np.ndarray:
         st[f] = amp * acc / modes
     st[PHR] += 1.0
     return st
+
+
+def gauge_transform(st: np.ndarray, alpha: np.ndarray) -> np.ndarray:
+    """A state's image under the lattice gauge transformation alpha_x (the symmetry
+    of Sec. 2): phi, Pi -> e^{i alpha} phi, e^{i alpha} Pi;  A_i -> A_i + alpha_x -
+    alpha_{x+i};  E unchanged."""
+    out = st.copy()
+    c, s = np.cos(alpha), np.sin(alpha)
+    for re, im in ((PHR, PHI), (PIR, PII)):
+        out[re] = c * st[re] - s * st[im]
+        out[im] = s * st[re] + c * st[im]
+    for i, axis in enumerate((2, 1, 0)):          # x, y, z are array axes 2, 1, 0
+        out[AX + i] = st[AX + i] + alpha - np.roll(alpha, -1, axis=axis)
+    return out
 
 
 def gauge_function(n: int | tuple, seed: int, amp=np.pi) -> np.ndarray:

@@ -13,21 +13,10 @@ import pytest
 from scipy.integrate import solve_ivp
 
 from tests import inputs as I
+from tests.inputs import gauge_transform
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ERAS = [(0.0, 0.0), (1.0, 0.0), (1.0, 1.0), (2.0, 0.0), (2.0, 1.0), (1.0, 0.5)]
-
-
-def gauge_transform(st, alpha):
-    """phi, Pi -> e^{i alpha} phi, e^{i alpha} Pi;  A_i -> A_i + alpha_x - alpha_{x+i}."""
-    out = st.copy()
-    c, s = np.cos(alpha), np.sin(alpha)
-    for re, im in ((I.PHR, I.PHI), (I.PIR, I.PII)):
-        out[re] = c * st[re] - s * st[im]
-        out[im] = s * st[re] + c * st[im]
-    for i, axis in enumerate((2, 1, 0)):          # x, y, z are array axes 2, 1, 0
-        out[I.AX + i] = st[I.AX + i] + alpha - np.roll(alpha, -1, axis=axis)
-    return out
 
 
 def khat2(k, n, dx):
