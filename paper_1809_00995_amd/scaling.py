@@ -100,6 +100,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--seeds", type=int, default=5)
+    ap.add_argument("--first-seed", type=int, default=100, help="seeds first-seed, first-seed + 1, ...")
     ap.add_argument("--cases", default=",".join(DEFAULT_CASES))
     ap.add_argument("--measure-every", type=int, default=10)
     ap.add_argument("--window", type=float, default=0.5,
@@ -109,12 +110,13 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--series", action="store_true", help="also store each run's observation series")
     args = ap.parse_args(argv)
-    result = {"n": args.n, "seeds": args.seeds, "cases": {}}
+    result = {"n": args.n, "seeds": args.seeds, "first_seed": args.first_seed, "cases": {}}
     for name in args.cases.split(","):
         era, s, cg = CASES[name]
         runs = []
         for k in range(args.seeds):
-            obs = evolve(args.n, era, s, seed=100 + k, measure_every=args.measure_every,
+            seed = args.first_seed + k
+            obs = evolve(args.n, era, s, seed=seed, measure_every=args.measure_every,
                          core_growth=cg)
             runs.append(fit(obs, args.window))
             if args.window2:
@@ -122,10 +124,11 @@ def main(argv=None):
                                  for k, v in fit(obs, args.window2).items()})
             if args.series:
                 runs[-1]["series"] = series(obs, args.n)
-            print(f"{name} seed {100 + k}: " + ", ".join(f"{a}={b:.4f}" for a, b in runs[-1].items() if a != "series"),
-                  flush=True)
+            runs[-1]["seed"] = seed
+            print(f"{name} seed {seed}: " + ", ".join(f"{a}={b:.4f}" for a, b in runs[-1].items()
+                                                      if a not in ("series", "seed")), flush=True)
         summary = {}
-        for key in (k for k in runs[0] if k != "series"):
+        for key in (k for k in runs[0] if k not in ("series", "seed")):
             vals = np.array([r[key] for r in runs])
             summary[key] = {"mean": float(np.mean(vals)),
                             "stderr": float(np.std(vals, ddof=1) / math.sqrt(len(vals)))
