@@ -118,16 +118,15 @@ __host__ __device__ __forceinline__ int plane_count(int layout) {
 }
 
 // sin and cos of a link angle.
-// Float: x = 2 pi k + r with k = rint(x / 2 pi) and r from 2 pi split in a high
-// and a low part (one fused multiply-add each, |r| <= pi to within half an ulp
-// of r), then the hardware sine and cosine of t = r / 2 pi in revolutions
-// (|t| <= 1/2 up to the rounding of x / 2 pi).  Measured on the GPU over 2^24 angles in [-40, 40]: absolute
-// error at most 4.3e-7, of which the reduction's roundings (of r twice, of the
-// float 1/(2 pi), of t) account for up to 4.6e-7 and the hardware for the
-// rest; half an ulp of an FP32 angle is 1.9e-6 at |x| = 40, so the stored
-// angle itself is uncertain by more wherever |x| > 4.  The minimax
-// polynomial scheme used for double below gives 1.5e-7 in float but costs
-// about 14 more instructions per link, 3 % of a pair of steps.
+// Float: x = 2 pi k + r with k = rint(x / 2 pi), r from 2 pi split in a high
+// and a low part (one fused multiply-add each), then the hardware sine and
+// cosine of t = r / 2 pi in revolutions (|t| <= 1/2 up to the rounding of
+// x / 2 pi).  The reduction's roundings (of r twice, of the float 1/(2 pi), of
+// t) are bounded by 4.6e-7; measured on the GPU over 2^24 angles in [-40, 40]
+// the whole error is at most 4.3e-7.  Half an ulp of an FP32 angle is 1.9e-6 at
+// |x| = 40, so the stored angle itself is uncertain by more wherever |x| > 4.
+// The minimax polynomial scheme used for double below gives 1.5e-7 in float
+// but costs about 14 more instructions per link, 3 % of a pair of steps.
 // Double: x = k pi + r with k = rint(x / pi), r = x - k pi from pi split in a
 // high and a low part, so |r| <= pi/2; then
 //   sin r = r + r^3 P(r^2),   cos r = 1 + r^2 Q(r^2),
